@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path: one step = one full gradient evaluation
+(fwi_gradient: forward sweep with checkpoints, residual and misfit, adjoint
+sweep with re-forward of each checkpoint segment, gradient imaging) for all
+shots of the workload, with inputs resident in device memory.
+
+Metric: forward + adjoint Gcell-updates/s = NX * NY * nt * shots * 2 / time,
+NX x NY the total grid including the CPML.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload large|survey|tiny]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2506_20513_amd import inputs as I  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, AMD public specification
+
+WORKLOADS = {"large": I.config_large, "survey": I.config_survey, "tiny": I.config_tiny}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(kernel: str, cells: int, shots: int) -> float:
+    """Bytes one launch must move by the method itself: a forward cell-update
+    reads and writes Ez, Hx, Hy (24 B); the adjoint also needs the forward
+    Ez^n (28 B).  Ca and Cs (8 B per cell) are shared by all shots."""
+    per = {"k_fwd_step": 24.0, "k_adj_step": 28.0}[kernel]
+    return cells * (per * shots + 8.0)
+
+
+def cpu_baseline(cfg, e0, s0, src, rec, w, steps: int):
+    """The FP64 oracle as it stands on the host cores: one shot of the same
+    grid, `steps` forward steps keeping the Ez history, then the adjoint
+    sweep over them."""
+    import oracle
+    P = oracle.Problem(e0, s0, cfg.npml, cfg.dx, cfg.dy, cfg.dt, cpml_order=cfg.cpml_order,
+                       cpml_sigma_scale=cfg.cpml_sigma_scale, cpml_kappa_max=cfg.cpml_kappa_max,
+                       cpml_alpha_max=cfg.cpml_alpha_max)
+    rng = np.random.default_rng(0)
+    res = rng.standard_normal((steps, cfg.nrec))
+    st = P.new_state()
+    t0 = time.perf_counter()
+    _, hist = P.run(st, 0, steps, src[0], w[0], rec[0], keep_history=True)
+    lam = P.new_state()
+    S1 = np.zeros((cfg.NY, cfg.NX))
+    S2 = np.zeros((cfg.NY, cfg.NX))
+    P.adjoint_run(lam, steps, 0, src[0], rec[0], res, hist, S1, S2)
+    P.finalize(S1, S2)
+    el = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = min(cores, os.cpu_count() or cores)
+    return {"value": cfg.NX * cfg.NY * steps * 2 / el / 1e9, "unit": "Gcell-updates/s",
+            "cores": cores, "kind": "oracle",
+            "sample": f"1 shot x {steps} steps of the {cfg.NX}x{cfg.NY} grid, forward "
+                      f"(Ez history kept) + adjoint + gradient, FP64, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
+    ap.add_argument("--sample-every", type=int, default=8,
+                    help="time every k-th launch of each hot kernel with HIP events")
+    ap.add_argument("--cpu-steps", type=int, default=600)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported: this build runs on one "
+              "GPU only (shots would shard across GPUs with one gradient all-reduce, "
+              "which is not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2506_20513_amd import fwi
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    fwi.lib()
+
+    cfg = WORKLOADS[args.workload]()
+    dev = "cuda"
+    log(f"bench: workload {cfg.name} NX={cfg.NX} NY={cfg.NY} nt={cfg.nt} shots={cfg.nshots} "
+        f"receivers={cfg.nrec}")
+    e, s, e0, s0 = I.model_for(cfg)
+    src, rec = I.geometry(cfg)
+    w = I.wavelets(cfg)
+    grid = fwi.grid_from_config(cfg)
+    wt = torch.from_numpy(w).to(dev)
+    geom = fwi.Geometry(src, rec, wt)
+    et, st_, e0t, s0t = (torch.from_numpy(a).to(dev) for a in (e, s, e0, s0))
+    S, R, nt = cfg.nshots, cfg.nrec, cfg.nt
+
+    # observed data: forward of the true model (input preparation, untimed)
+    ws_fwd = fwi.alloc_workspace(fwi.workspace_bytes(grid, geom, fwi.FWI_SAVE_NONE), dev)
+    obs = torch.empty((S, nt, R), device=dev)
+    fwi.fdtd_forward(grid, geom, et, st_, obs, fwi.FWI_SAVE_NONE, ws_fwd)
+    torch.cuda.synchronize()
+    del ws_fwd
+    log("bench: observed data ready")
+
+    ws_bytes = fwi.workspace_bytes(grid, geom, fwi.GRADIENT_WORKSPACE)
+    ws = fwi.alloc_workspace(ws_bytes, dev)
+    K = fwi.checkpoint_interval(grid, geom)
+    mis = torch.empty(1, dtype=torch.float64, device=dev)
+    ge = torch.empty((cfg.NY, cfg.NX), device=dev)
+    gs = torch.empty((cfg.NY, cfg.NX), device=dev)
+    log(f"bench: workspace {ws_bytes / 1e9:.1f} GB, checkpoint interval {K}")
+
+    for k in range(args.warmup):
+        fwi.fwi_gradient(grid, geom, e0t, s0t, obs, mis, ge, gs, None, ws)
+        torch.cuda.synchronize()
+        log(f"bench: warmup {k + 1}/{args.warmup} done, misfit {mis.item():.6e}")
+
+    kt = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        tm = fwi.fwi_timing(sample_every=args.sample_every)
+        fwi.fwi_gradient_timed(grid, geom, e0t, s0t, obs, mis, ge, gs, None, ws, tm)
+        for name, v in tm.as_dict().items():
+            a = kt.setdefault(name, {"launches": 0, "timed": 0, "ms": 0.0})
+            a["launches"] += v["launches"]
+            a["timed"] += v["timed"]
+            a["ms"] += v["avg_ms"] * v["timed"]
+        log(f"bench: step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_per_step = el / args.steps * 1e3
+
+    cells = cfg.NX * cfg.NY
+    updates = cells * nt * S * 2
+    value = updates / (ms_per_step / 1e3) / 1e9
+    kernels = {}
+    for name, a in kt.items():
+        avg = a["ms"] / a["timed"] if a["timed"] else 0.0
+        kernels[name] = {"launches_per_step": a["launches"] // args.steps,
+                         "avg_ms": avg,
+                         "ms_per_step": avg * a["launches"] / args.steps}
+    dom = max((k for k in kernels if k in ("k_fwd_step", "k_adj_step")),
+              key=lambda k: kernels[k]["ms_per_step"])
+    by = algorithmic_bytes(dom, cells, S)
+    achieved = by / (kernels[dom]["avg_ms"] / 1e3) / 1e9
+    for name in kernels:
+        if name in ("k_fwd_step", "k_adj_step"):
+            kernels[name]["algorithmic_GBps"] = (algorithmic_bytes(name, cells, S)
+                                                 / (kernels[name]["avg_ms"] / 1e3) / 1e9)
+    # algorithmic bytes of the whole step (forward + adjoint, one pass each)
+    alg_step = cells * nt * (S * (24.0 + 28.0) + 16.0)
+    out = {
+        "metric": "Gcell-updates/s fwd+adjoint FDTD (eps_r/sigma gradient)",
+        "value": round(value, 3),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {cfg.nx}x{cfg.ny} interior + {cfg.npml}-cell CPML "
+                               f"({cfg.NX}x{cfg.NY}), dx={cfg.dx} m, {nt} steps, "
+                               f"{S} shots x {R} receivers, Ricker {cfg.f0 / 1e6:.0f} MHz",
+                   "grid": [cfg.NX, cfg.NY], "nt": nt, "shots": S, "receivers": R,
+                   "checkpoint_interval": K, "workspace_GB": round(ws_bytes / 1e9, 2)},
+        "s_per_shot_gradient": round(ms_per_step / 1e3 / S, 5),
+        "interior_gcells": round(cfg.nx * cfg.ny * nt * S * 2 / (ms_per_step / 1e3) / 1e9, 3),
+        "effective_hbm_frac": round(alg_step / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None,
+                     "bytes_per_launch": by},
+        "kernels": kernels,
+        "misfit": float(mis.item()),
+    }
+    if not args.no_cpu_baseline:
+        log(f"bench: cpu baseline (oracle, {args.cpu_steps} steps of one shot)")
+        del ws
+        torch.cuda.empty_cache()
+        out["cpu_baseline"] = cpu_baseline(cfg, e0, s0, src, rec, w,
+                                           min(args.cpu_steps, nt))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

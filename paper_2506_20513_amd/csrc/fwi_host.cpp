@@ -1,0 +1,618 @@
+// Host side of the FWI library: argument validation (pure host code, runs
+// before any HIP call), workspace layout, and the time loops of the forward
+// sweep (Algorithm 1), the adjoint sweep (Algorithm 2) and the full gradient
+// evaluation.  Paper: arXiv 2506.20513, Secs. 2.1 and 3.3.
+#include "fwi.h"
+#include "fwi_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+namespace fwi {
+namespace {
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Grid checks: shapes, spacings, CFL bound (Eq. (11) with c = c0, the fastest
+// speed any model with eps_r >= 1 can have), CPML parameters.
+int check_grid(const fwi_grid *g) {
+    if (!g) return FWI_EINVAL;
+    if (g->nx < 1 || g->ny < 1 || g->npml < 0 || g->nt < 1) return FWI_EINVAL;
+    const int64_t NX = (int64_t)g->nx + 2 * (int64_t)g->npml;
+    const int64_t NY = (int64_t)g->ny + 2 * (int64_t)g->npml;
+    if (NX < 3 || NY < 3 || NX > (1 << 20) || NY > (1 << 20)) return FWI_EINVAL;
+    if (!finite_pos(g->dx) || !finite_pos(g->dy) || !finite_pos(g->dt)) return FWI_EINVAL;
+    if (g->cpml_order < 1 || g->cpml_order > 16) return FWI_EINVAL;
+    if (!std::isfinite(g->cpml_sigma_scale) || g->cpml_sigma_scale < 0.0) return FWI_EINVAL;
+    if (!std::isfinite(g->cpml_kappa_max) || g->cpml_kappa_max < 1.0) return FWI_EINVAL;
+    if (!std::isfinite(g->cpml_alpha_max) || g->cpml_alpha_max < 0.0) return FWI_EINVAL;
+    const double bound = 1.0 / (kC0 * std::sqrt(1.0 / (g->dx * g->dx) + 1.0 / (g->dy * g->dy)));
+    if (g->dt > bound * (1.0 + 1e-12)) return FWI_ECFL;
+    return FWI_OK;
+}
+
+bool inside(int i, int j, const Dims &d) {
+    const int lo_i = std::max(d.npml, 1), hi_i = std::min(d.NX - 1 - d.npml, d.NX - 2);
+    const int lo_j = std::max(d.npml, 1), hi_j = std::min(d.NY - 1 - d.npml, d.NY - 2);
+    return i >= lo_i && i <= hi_i && j >= lo_j && j <= hi_j;
+}
+
+int check_geom(const fwi_geom *g, Dims &d) {
+    if (!g) return FWI_EINVAL;
+    if (g->nshots < 1 || g->nrec < 1) return FWI_EINVAL;
+    if ((int64_t)g->nshots * g->nrec > (1 << 28)) return FWI_EINVAL;
+    if (!g->src_ij || !g->rec_ij || !g->wavelet) return FWI_EINVAL;
+    d.S = g->nshots;
+    d.R = g->nrec;
+    for (int s = 0; s < d.S; ++s)
+        if (!inside(g->src_ij[2 * s], g->src_ij[2 * s + 1], d)) return FWI_EGEOM;
+    const size_t nr = (size_t)d.S * d.R;
+    for (size_t t = 0; t < nr; ++t)
+        if (!inside(g->rec_ij[2 * t], g->rec_ij[2 * t + 1], d)) return FWI_EGEOM;
+    return FWI_OK;
+}
+
+int make_dims(const fwi_grid *grid, const fwi_geom *geom, Dims &d) {
+    int st = check_grid(grid);
+    if (st != FWI_OK) return st;
+    d.npml = grid->npml;
+    d.nt = grid->nt;
+    d.NX = grid->nx + 2 * grid->npml;
+    d.NY = grid->ny + 2 * grid->npml;
+    d.pitch = (d.NX + 63) / 64 * 64;
+    d.W = 2 * d.npml + 1;
+    d.Hs = 2 * d.npml + 1;
+    d.plane = (size_t)d.NY * d.pitch;
+    d.xs = (size_t)d.NY * d.W;
+    d.ys = (size_t)d.Hs * d.pitch;
+    d.dx = grid->dx;
+    d.dy = grid->dy;
+    d.dt = grid->dt;
+    d.cpml_order = grid->cpml_order;
+    d.cpml_sigma_scale = grid->cpml_sigma_scale;
+    d.cpml_kappa_max = grid->cpml_kappa_max;
+    d.cpml_alpha_max = grid->cpml_alpha_max;
+    return check_geom(geom, d);
+}
+
+// Checkpoint interval minimising checkpoints + segment buffer:
+// ceil(nt/K) * C + (K+1) * E with C one full state and E one Ez slot.
+int choose_k(const Dims &d) {
+    const double C = 3.0 * d.plane + 2.0 * d.xs + 2.0 * d.ys;
+    const double E = (double)d.plane;
+    int K = (int)std::lround(std::sqrt((double)d.nt * C / E));
+    return std::max(1, std::min(K, d.nt));
+}
+
+// Workspace layout for a mode (FWI_SAVE_* or -1 = fwi_gradient).
+int make_layout(const Dims &d, int mode, Layout &L) {
+    if (mode != FWI_SAVE_NONE && mode != FWI_SAVE_CHECKPOINT &&
+        mode != FWI_SAVE_HISTORY && mode != -1)
+        return FWI_EINVAL;
+    L.d = d;
+    L.mode = mode;
+    const size_t S = (size_t)d.S;
+    const size_t field = S * d.plane * sizeof(float);
+    const size_t xs = S * d.xs * sizeof(float), ys = S * d.ys * sizeof(float);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    L.off_Ca = take(d.plane * sizeof(float));
+    L.off_Cs = take(d.plane * sizeof(float));
+    L.off_prof = take((size_t)6 * (d.NX + d.NY) * sizeof(float));
+    L.off_src = take(S * 2 * sizeof(int));
+    L.off_rec = take(S * d.R * 2 * sizeof(int));
+    L.off_rord = take(S * d.R * sizeof(int));
+    L.off_rlen = take(S * d.R * sizeof(int));
+    L.state_bytes = align_up(field) * 2 + align_up(xs) * 2 + align_up(ys) * 2;
+    L.off_fwd[0] = take(L.state_bytes);
+    L.off_fwd[1] = take(L.state_bytes);
+    L.K = 0;
+    L.ncp = 0;
+    L.ckpt_stride = 0;
+    L.off_ckpt = 0;
+    if (mode == FWI_SAVE_NONE) {
+        L.nslots = 2;
+    } else if (mode == FWI_SAVE_HISTORY) {
+        L.nslots = d.nt + 1;
+    } else {
+        L.K = choose_k(d);
+        L.ncp = (d.nt + L.K - 1) / L.K;
+        L.nslots = L.K + 1;
+    }
+    if ((double)L.nslots * (double)field > 1e15) return FWI_EINVAL;
+    L.off_slots = take((size_t)L.nslots * field);
+    if (L.ncp > 0) {
+        L.ckpt_stride = align_up(field) + L.state_bytes;
+        L.off_ckpt = take((size_t)L.ncp * L.ckpt_stride);
+    }
+    L.off_adj[0] = L.off_adj[1] = L.off_S1 = L.off_S2 = 0;
+    if (mode != FWI_SAVE_NONE) {
+        L.off_adj[0] = take(align_up(field) + L.state_bytes);
+        L.off_adj[1] = take(align_up(field) + L.state_bytes);
+        L.off_S1 = take(d.plane * sizeof(float));
+        L.off_S2 = take(d.plane * sizeof(float));
+    }
+    L.off_res = L.off_trc = L.off_mis = 0;
+    if (mode == -1) {
+        const size_t tr = S * d.R * (size_t)d.nt * sizeof(float);
+        L.off_res = take(tr);
+        L.off_trc = take(tr);
+        L.off_mis = take(kMisfitBlocks * sizeof(double));
+    }
+    L.total = off;
+    return FWI_OK;
+}
+
+// Pointers into the workspace.
+struct Ptrs {
+    char *base;
+    const Layout *L;
+    float *f(size_t off) const { return reinterpret_cast<float *>(base + off); }
+    int *i(size_t off) const { return reinterpret_cast<int *>(base + off); }
+    Profiles prof() const {
+        const Dims &d = L->d;
+        float *p = f(L->off_prof);
+        Profiles q;
+        q.bEx = p; q.aEx = p + d.NX; q.kEx = p + 2 * d.NX;
+        q.bHx = p + 3 * d.NX; q.aHx = p + 4 * d.NX; q.kHx = p + 5 * d.NX;
+        float *y = p + 6 * d.NX;
+        q.bEy = y; q.aEy = y + d.NY; q.kEy = y + 2 * d.NY;
+        q.bHy = y + 3 * d.NY; q.aHy = y + 4 * d.NY; q.kHy = y + 5 * d.NY;
+        return q;
+    }
+    // A State laid out at `off`: [E][Hx][Hy][phx][phy][pex][pey] (E only when
+    // with_e).
+    State state(size_t off, bool with_e) const {
+        const Dims &d = L->d;
+        const size_t S = (size_t)d.S;
+        const size_t field = align_up(S * d.plane * sizeof(float));
+        const size_t xs = align_up(S * d.xs * sizeof(float));
+        const size_t ys = align_up(S * d.ys * sizeof(float));
+        State st;
+        size_t o = off;
+        st.E = nullptr;
+        if (with_e) { st.E = f(o); o += field; }
+        st.Hx = f(o); o += field;
+        st.Hy = f(o); o += field;
+        st.phx = f(o); o += ys;
+        st.phy = f(o); o += xs;
+        st.pex = f(o); o += xs;
+        st.pey = f(o);
+        return st;
+    }
+    float *slot(int k) const {
+        const Dims &d = L->d;
+        return f(L->off_slots) + (size_t)k * d.S * d.plane;
+    }
+};
+
+#define FWI_TRY(expr)                                   \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess) return FWI_EHIP;          \
+    } while (0)
+
+// Optional per-kernel timing with HIP events on the call's stream.
+enum Kind { K_FWD = 0, K_ADJ = 1, K_INJ = 2, K_NKINDS = 3 };
+const char *const kKindName[K_NKINDS] = {"k_fwd_step", "k_adj_step", "k_adj_inject"};
+
+struct Timer {
+    fwi_timing *t = nullptr;
+    hipStream_t st = nullptr;
+    int launches[K_NKINDS] = {0, 0, 0};
+    struct Rec { int kind; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+    bool failed = false;
+
+    // Launch `fn` (returning hipError_t), bracketed by events when sampled.
+    template <class F>
+    hipError_t run(int kind, F fn) {
+        const int idx = launches[kind]++;
+        if (!t || idx % t->sample_every != 0 || failed) return fn();
+        Rec r{kind, nullptr, nullptr};
+        if (hipEventCreate(&r.a) != hipSuccess) { failed = true; return fn(); }
+        if (hipEventCreate(&r.b) != hipSuccess) {
+            hipEventDestroy(r.a);
+            failed = true;
+            return fn();
+        }
+        hipError_t e = hipEventRecord(r.a, st);
+        if (e == hipSuccess) e = fn();
+        if (e == hipSuccess) e = hipEventRecord(r.b, st);
+        recs.push_back(r);
+        return e;
+    }
+
+    int finish() {
+        if (!t) return FWI_OK;
+        double sum[K_NKINDS] = {0, 0, 0};
+        int cnt[K_NKINDS] = {0, 0, 0};
+        int rc = FWI_OK;
+        if (hipStreamSynchronize(st) != hipSuccess) rc = FWI_EHIP;
+        for (auto &r : recs) {
+            float ms = 0.f;
+            if (rc == FWI_OK && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+                sum[r.kind] += ms;
+                cnt[r.kind] += 1;
+            }
+            hipEventDestroy(r.a);
+            hipEventDestroy(r.b);
+        }
+        recs.clear();
+        t->nkinds = K_NKINDS;
+        for (int k = 0; k < K_NKINDS; ++k) {
+            fwi_kernel_time &o = t->kind[k];
+            std::memset(o.name, 0, sizeof(o.name));
+            std::strncpy(o.name, kKindName[k], sizeof(o.name) - 1);
+            o.launches = launches[k];
+            o.timed = cnt[k];
+            o.avg_ms = cnt[k] ? sum[k] / cnt[k] : 0.0;
+        }
+        return rc;
+    }
+};
+
+// Geometry to the device, plus receivers grouped by cell for the adjoint
+// source (sorted by cell, stable in receiver index).
+int upload_geometry(const Ptrs &P, const fwi_geom *g, hipStream_t st) {
+    const Dims &d = P.L->d;
+    const size_t S = d.S, R = d.R;
+    std::vector<int> order(S * R), glen(S * R, 0);
+    for (size_t s = 0; s < S; ++s) {
+        const int32_t *rc = g->rec_ij + 2 * s * R;
+        int *o = order.data() + s * R;
+        std::iota(o, o + R, 0);
+        std::stable_sort(o, o + R, [&](int a, int b) {
+            const int64_t ka = (int64_t)rc[2 * a + 1] * d.NX + rc[2 * a];
+            const int64_t kb = (int64_t)rc[2 * b + 1] * d.NX + rc[2 * b];
+            return ka < kb;
+        });
+        size_t p = 0;
+        while (p < R) {
+            size_t q = p + 1;
+            while (q < R && rc[2 * o[q]] == rc[2 * o[p]] && rc[2 * o[q] + 1] == rc[2 * o[p] + 1]) ++q;
+            glen[s * R + p] = (int)(q - p);
+            p = q;
+        }
+    }
+    FWI_TRY(hipMemcpyAsync(P.i(P.L->off_src), g->src_ij, S * 2 * sizeof(int),
+                           hipMemcpyHostToDevice, st));
+    FWI_TRY(hipMemcpyAsync(P.i(P.L->off_rec), g->rec_ij, S * R * 2 * sizeof(int),
+                           hipMemcpyHostToDevice, st));
+    FWI_TRY(hipMemcpyAsync(P.i(P.L->off_rord), order.data(), S * R * sizeof(int),
+                           hipMemcpyHostToDevice, st));
+    FWI_TRY(hipMemcpyAsync(P.i(P.L->off_rlen), glen.data(), S * R * sizeof(int),
+                           hipMemcpyHostToDevice, st));
+    // pageable host sources: make sure the copies consumed them before the
+    // vectors go out of scope
+    FWI_TRY(hipStreamSynchronize(st));
+    return FWI_OK;
+}
+
+int zero_state(const State &s, const Dims &d, bool with_e, hipStream_t st) {
+    const size_t S = d.S;
+    if (with_e) FWI_TRY(launch_fill(s.E, S * d.plane, 0.f, st));
+    FWI_TRY(launch_fill(s.Hx, S * d.plane, 0.f, st));
+    FWI_TRY(launch_fill(s.Hy, S * d.plane, 0.f, st));
+    FWI_TRY(launch_fill(s.phx, S * d.ys, 0.f, st));
+    FWI_TRY(launch_fill(s.phy, S * d.xs, 0.f, st));
+    FWI_TRY(launch_fill(s.pex, S * d.xs, 0.f, st));
+    FWI_TRY(launch_fill(s.pey, S * d.ys, 0.f, st));
+    return FWI_OK;
+}
+
+int copy_state(const State &dst, const State &src, const Dims &d, hipStream_t st) {
+    const size_t S = d.S;
+    const size_t f = S * d.plane * sizeof(float);
+    FWI_TRY(hipMemcpyAsync(dst.Hx, src.Hx, f, hipMemcpyDeviceToDevice, st));
+    FWI_TRY(hipMemcpyAsync(dst.Hy, src.Hy, f, hipMemcpyDeviceToDevice, st));
+    FWI_TRY(hipMemcpyAsync(dst.phx, src.phx, S * d.ys * sizeof(float), hipMemcpyDeviceToDevice, st));
+    FWI_TRY(hipMemcpyAsync(dst.phy, src.phy, S * d.xs * sizeof(float), hipMemcpyDeviceToDevice, st));
+    FWI_TRY(hipMemcpyAsync(dst.pex, src.pex, S * d.xs * sizeof(float), hipMemcpyDeviceToDevice, st));
+    FWI_TRY(hipMemcpyAsync(dst.pey, src.pey, S * d.ys * sizeof(float), hipMemcpyDeviceToDevice, st));
+    return FWI_OK;
+}
+
+FwdStepArgs fwd_args(const Ptrs &P, const fwi_geom *g) {
+    const Dims &d = P.L->d;
+    FwdStepArgs a;
+    a.NX = d.NX; a.NY = d.NY; a.npml = d.npml; a.pitch = d.pitch;
+    a.W = d.W; a.Hs = d.Hs; a.S = d.S; a.R = d.R; a.nt = d.nt; a.n = 0;
+    a.plane = d.plane; a.xs = d.xs; a.ys = d.ys;
+    a.rdx = (float)(1.0 / d.dx);
+    a.rdy = (float)(1.0 / d.dy);
+    a.ch = (float)(d.dt / kMu0);
+    a.src_scale = (float)(1.0 / (d.dx * d.dy));
+    a.Ca = P.f(P.L->off_Ca);
+    a.Cs = P.f(P.L->off_Cs);
+    a.p = P.prof();
+    a.g.src_ij = P.i(P.L->off_src);
+    a.g.wavelet = g->wavelet;
+    a.g.rec_ij = P.i(P.L->off_rec);
+    a.g.traces = nullptr;
+    return a;
+}
+
+// Coefficients, profiles, geometry; forward state cleared.
+int setup(const Ptrs &P, const fwi_geom *g, const float *eps_r, const float *sigma,
+          hipStream_t st) {
+    const Dims &d = P.L->d;
+    int rc = upload_geometry(P, g, st);
+    if (rc != FWI_OK) return rc;
+    FWI_TRY(launch_coefficients(eps_r, sigma, P.f(P.L->off_Ca), P.f(P.L->off_Cs), d.NX,
+                                d.NY, d.pitch, d.dt, st));
+    FWI_TRY(launch_profiles(d, P.prof(), st));
+    return FWI_OK;
+}
+
+// Run forward steps [n0, n1).  E of step n is read from ein(n) and written
+// to eout(n); the H / CPML state ping-pongs between fwd[0] and fwd[1]
+// starting at fwd[cur].  Returns the index of the state holding the result.
+template <class EIn, class EOut>
+int forward_steps(const Ptrs &P, FwdStepArgs a, int n0, int n1, int &cur, EIn ein,
+                  EOut eout, float *traces, hipStream_t st, Timer &tm) {
+    State fs[2] = {P.state(P.L->off_fwd[0], false), P.state(P.L->off_fwd[1], false)};
+    a.g.traces = traces;
+    for (int n = n0; n < n1; ++n) {
+        a.n = n;
+        a.E_in = ein(n);
+        a.E_out = eout(n);
+        a.in = fs[cur];
+        a.out = fs[cur ^ 1];
+        FWI_TRY(tm.run(K_FWD, [&] { return launch_fwd_step(a, st); }));
+        cur ^= 1;
+    }
+    return FWI_OK;
+}
+
+int do_forward(const Layout &L, const fwi_geom *g, const float *eps_r,
+               const float *sigma, float *traces, void *ws, hipStream_t st,
+               Timer &tm) {
+    const Dims &d = L.d;
+    Ptrs P{static_cast<char *>(ws), &L};
+    int rc = setup(P, g, eps_r, sigma, st);
+    if (rc != FWI_OK) return rc;
+    State fs0 = P.state(L.off_fwd[0], false);
+    rc = zero_state(fs0, d, false, st);
+    if (rc != FWI_OK) return rc;
+    FWI_TRY(launch_fill(P.slot(0), (size_t)d.S * d.plane, 0.f, st));
+    FwdStepArgs a = fwd_args(P, g);
+    int cur = 0;
+    if (L.mode == FWI_SAVE_HISTORY) {
+        return forward_steps(
+            P, a, 0, d.nt, cur, [&](int n) { return P.slot(n); },
+            [&](int n) { return P.slot(n + 1); }, traces, st, tm);
+    }
+    // ping-pong E between slots 0 and 1; checkpoint (E, H, psi) every K steps
+    const int K = L.mode == FWI_SAVE_CHECKPOINT || L.mode == -1 ? L.K : d.nt;
+    for (int n0 = 0; n0 < d.nt; n0 += K) {
+        const int n1 = std::min(d.nt, n0 + K);
+        if (L.ncp > 0) {
+            const int c = n0 / K;
+            char *cp = static_cast<char *>(ws) + L.off_ckpt + (size_t)c * L.ckpt_stride;
+            const size_t f = (size_t)d.S * d.plane * sizeof(float);
+            FWI_TRY(hipMemcpyAsync(cp, P.slot(n0 & 1), f, hipMemcpyDeviceToDevice, st));
+            State cst = P.state(L.off_ckpt + (size_t)c * L.ckpt_stride + align_up(f), false);
+            rc = copy_state(cst, P.state(L.off_fwd[cur], false), d, st);
+            if (rc != FWI_OK) return rc;
+        }
+        rc = forward_steps(
+            P, a, n0, n1, cur, [&](int n) { return P.slot(n & 1); },
+            [&](int n) { return P.slot((n + 1) & 1); }, traces, st, tm);
+        if (rc != FWI_OK) return rc;
+    }
+    return FWI_OK;
+}
+
+int do_adjoint(const Layout &L, const fwi_geom *g, const float *eps_r,
+               const float *sigma, const float *residual, float *g_eps,
+               float *g_sig, float *src_adj, void *ws, hipStream_t st, Timer &tm) {
+    const Dims &d = L.d;
+    Ptrs P{static_cast<char *>(ws), &L};
+    State as[2] = {P.state(L.off_adj[0], true), P.state(L.off_adj[1], true)};
+    int rc = zero_state(as[0], d, true, st);
+    if (rc != FWI_OK) return rc;
+    float *S1 = P.f(L.off_S1), *S2 = P.f(L.off_S2);
+    FWI_TRY(launch_fill(S1, d.plane, 0.f, st));
+    FWI_TRY(launch_fill(S2, d.plane, 0.f, st));
+
+    AdjStepArgs a;
+    a.NX = d.NX; a.NY = d.NY; a.npml = d.npml; a.pitch = d.pitch;
+    a.W = d.W; a.Hs = d.Hs; a.S = d.S; a.R = d.R; a.nt = d.nt;
+    a.plane = d.plane; a.xs = d.xs; a.ys = d.ys;
+    a.rdx = (float)(1.0 / d.dx);
+    a.rdy = (float)(1.0 / d.dy);
+    a.ch = (float)(d.dt / kMu0);
+    a.src_scale = (float)(1.0 / (d.dx * d.dy));
+    a.Ca = P.f(L.off_Ca);
+    a.Cs = P.f(L.off_Cs);
+    a.p = P.prof();
+    a.S1 = S1;
+    a.S2 = S2;
+    a.src_ij = P.i(L.off_src);
+    a.src_adjoint = src_adj;
+    int acur = 0;
+    auto adj_range = [&](int n_hi, int n_lo, auto eslot) -> int {
+        for (int n = n_hi - 1; n >= n_lo; --n) {
+            a.n = n;
+            a.E_np1 = eslot(n + 1);
+            a.E_n = eslot(n);
+            a.in = as[acur];
+            a.out = as[acur ^ 1];
+            FWI_TRY(tm.run(K_ADJ, [&] { return launch_adj_step(a, st); }));
+            FWI_TRY(tm.run(K_INJ, [&] {
+                return launch_adj_inject(residual, as[acur ^ 1].E, P.i(L.off_rec),
+                                         P.i(L.off_rord), P.i(L.off_rlen), d.S, d.R,
+                                         d.nt, n, d.plane, d.pitch, st);
+            }));
+            acur ^= 1;
+        }
+        return FWI_OK;
+    };
+
+    if (L.mode == FWI_SAVE_HISTORY) {
+        rc = adj_range(d.nt, 0, [&](int n) { return P.slot(n); });
+        if (rc != FWI_OK) return rc;
+    } else {
+        // segment by segment, last first: restore the checkpoint, re-run the
+        // segment forward into slots 0..K, then run the adjoint through it
+        FwdStepArgs fa = fwd_args(P, g);
+        const size_t f = (size_t)d.S * d.plane * sizeof(float);
+        for (int c = L.ncp - 1; c >= 0; --c) {
+            const int n0 = c * L.K, n1 = std::min(d.nt, n0 + L.K);
+            const size_t co = L.off_ckpt + (size_t)c * L.ckpt_stride;
+            FWI_TRY(hipMemcpyAsync(P.slot(0), P.base + co, f, hipMemcpyDeviceToDevice, st));
+            rc = copy_state(P.state(L.off_fwd[0], false), P.state(co + align_up(f), false), d, st);
+            if (rc != FWI_OK) return rc;
+            int cur = 0;
+            rc = forward_steps(
+                P, fa, n0, n1, cur, [&](int n) { return P.slot(n - n0); },
+                [&](int n) { return P.slot(n + 1 - n0); }, nullptr, st, tm);
+            if (rc != FWI_OK) return rc;
+            rc = adj_range(n1, n0, [&](int n) { return P.slot(n - n0); });
+            if (rc != FWI_OK) return rc;
+        }
+    }
+    FWI_TRY(launch_gradient_finalize(eps_r, sigma, S1, S2, g_eps, g_sig, d.NX, d.NY,
+                                     d.pitch, d.dt, st));
+    return FWI_OK;
+}
+
+int prepare(const fwi_grid *grid, const fwi_geom *geom, int mode, void *ws,
+            size_t ws_bytes, Layout &L) {
+    Dims d;
+    int rc = make_dims(grid, geom, d);
+    if (rc != FWI_OK) return rc;
+    rc = make_layout(d, mode, L);
+    if (rc != FWI_OK) return rc;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0 || ws_bytes < L.total)
+        return FWI_ENOMEM;
+    return FWI_OK;
+}
+
+}  // namespace
+}  // namespace fwi
+
+using namespace fwi;
+
+extern "C" int fwi_workspace_bytes(const fwi_grid *grid, const fwi_geom *geom,
+                                   int save_mode, size_t *bytes) {
+    if (!bytes) return FWI_EINVAL;
+    Dims d;
+    int rc = make_dims(grid, geom, d);
+    if (rc != FWI_OK) return rc;
+    Layout L;
+    rc = make_layout(d, save_mode, L);
+    if (rc != FWI_OK) return rc;
+    *bytes = L.total;
+    return FWI_OK;
+}
+
+extern "C" int fwi_checkpoint_interval(const fwi_grid *grid, const fwi_geom *geom,
+                                       int32_t *k) {
+    if (!k) return FWI_EINVAL;
+    Dims d;
+    int rc = make_dims(grid, geom, d);
+    if (rc != FWI_OK) return rc;
+    *k = choose_k(d);
+    return FWI_OK;
+}
+
+extern "C" int fdtd_forward(const fwi_grid *grid, const fwi_geom *geom,
+                            const float *eps_r, const float *sigma, float *traces,
+                            int save_mode, void *ws, size_t ws_bytes, void *stream) {
+    if (save_mode != FWI_SAVE_NONE && save_mode != FWI_SAVE_CHECKPOINT &&
+        save_mode != FWI_SAVE_HISTORY)
+        return FWI_EINVAL;
+    if (!eps_r || !sigma || !traces) return FWI_EINVAL;
+    Layout L;
+    int rc = prepare(grid, geom, save_mode, ws, ws_bytes, L);
+    if (rc != FWI_OK) return rc;
+    Timer tm;
+    return do_forward(L, geom, eps_r, sigma, traces, ws, static_cast<hipStream_t>(stream), tm);
+}
+
+extern "C" int fdtd_adjoint(const fwi_grid *grid, const fwi_geom *geom,
+                            const float *eps_r, const float *sigma,
+                            const float *residual, float *grad_eps_r,
+                            float *grad_sigma, float *src_adjoint, int save_mode,
+                            void *ws, size_t ws_bytes, void *stream) {
+    if (save_mode != FWI_SAVE_CHECKPOINT && save_mode != FWI_SAVE_HISTORY)
+        return FWI_EINVAL;
+    if (!eps_r || !sigma || !residual || !grad_eps_r || !grad_sigma) return FWI_EINVAL;
+    Layout L;
+    int rc = prepare(grid, geom, save_mode, ws, ws_bytes, L);
+    if (rc != FWI_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Ptrs P{static_cast<char *>(ws), &L};
+    rc = upload_geometry(P, geom, st);
+    if (rc != FWI_OK) return rc;
+    Timer tm;
+    return do_adjoint(L, geom, eps_r, sigma, residual, grad_eps_r, grad_sigma,
+                      src_adjoint, ws, st, tm);
+}
+
+extern "C" int fwi_gradient_timed(const fwi_grid *grid, const fwi_geom *geom,
+                                  const float *eps_r, const float *sigma,
+                                  const float *observed, double *misfit,
+                                  float *grad_eps_r, float *grad_sigma,
+                                  float *traces_out, void *ws, size_t ws_bytes,
+                                  void *stream, fwi_timing *timing) {
+    if (!eps_r || !sigma || !observed || !misfit || !grad_eps_r || !grad_sigma)
+        return FWI_EINVAL;
+    if (timing && timing->sample_every < 1) return FWI_EINVAL;
+    Layout L;
+    int rc = prepare(grid, geom, -1, ws, ws_bytes, L);
+    if (rc != FWI_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Ptrs P{static_cast<char *>(ws), &L};
+    const Dims &d = L.d;
+    Timer tm;
+    tm.t = timing;
+    tm.st = st;
+    float *traces = traces_out ? traces_out : P.f(L.off_trc);
+    rc = do_forward(L, geom, eps_r, sigma, traces, ws, st, tm);
+    if (rc == FWI_OK) {
+        const size_t ntr = (size_t)d.S * d.nt * d.R;
+        float *res = P.f(L.off_res);
+        if (launch_residual_misfit(traces, observed, res, ntr,
+                                   reinterpret_cast<double *>(P.base + L.off_mis), misfit,
+                                   st) != hipSuccess)
+            rc = FWI_EHIP;
+        if (rc == FWI_OK)
+            rc = do_adjoint(L, geom, eps_r, sigma, res, grad_eps_r, grad_sigma, nullptr, ws,
+                            st, tm);
+    }
+    const int rc2 = tm.finish();
+    return rc != FWI_OK ? rc : rc2;
+}
+
+extern "C" int fwi_gradient(const fwi_grid *grid, const fwi_geom *geom,
+                            const float *eps_r, const float *sigma,
+                            const float *observed, double *misfit,
+                            float *grad_eps_r, float *grad_sigma, float *traces_out,
+                            void *ws, size_t ws_bytes, void *stream) {
+    return fwi_gradient_timed(grid, geom, eps_r, sigma, observed, misfit, grad_eps_r,
+                              grad_sigma, traces_out, ws, ws_bytes, stream, nullptr);
+}
+
+extern "C" const char *fwi_strerror(int status) {
+    switch (status) {
+        case FWI_OK: return "ok";
+        case FWI_EINVAL: return "invalid argument (null pointer, size or parameter)";
+        case FWI_ECFL: return "time step exceeds the CFL stability bound";
+        case FWI_EGEOM: return "source or receiver outside the updated interior";
+        case FWI_ENOMEM: return "workspace missing, misaligned or too small";
+        case FWI_EHIP: return "HIP runtime or kernel launch failure";
+        default: return "unknown status";
+    }
+}

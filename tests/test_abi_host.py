@@ -1,0 +1,166 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/fwi.h declares, sizes workspaces, and rejects bad
+arguments with the documented status before any HIP call.  Every call here
+is invalid on purpose or purely host-side (sizes), so nothing reaches the
+GPU runtime."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2506_20513_amd import fwi
+from paper_2506_20513_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fwi.h")
+
+FAKE = 1 << 20        # a non-null, 256-aligned address that is never dereferenced
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
+
+
+def test_library_exports_every_declared_function():
+    names = header_functions()
+    assert set(names) == set(fwi.EXPORTED), names
+    L = ctypes.CDLL(fwi.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_strerror_covers_codes():
+    for code in (0, -1, -2, -3, -4, -5):
+        assert fwi.strerror(code) != "unknown status"
+    assert fwi.strerror(-99) == "unknown status"
+
+
+def _tiny():
+    cfg = I.config_tiny()
+    src, rec = I.geometry(cfg)
+    return cfg, fwi.grid_from_config(cfg), fwi.Geometry(src, rec, FAKE)
+
+
+def test_workspace_sizes_and_checkpoint_interval():
+    cfg, grid, geom = _tiny()
+    none = fwi.workspace_bytes(grid, geom, fwi.FWI_SAVE_NONE)
+    ck = fwi.workspace_bytes(grid, geom, fwi.FWI_SAVE_CHECKPOINT)
+    hist = fwi.workspace_bytes(grid, geom, fwi.FWI_SAVE_HISTORY)
+    grad = fwi.workspace_bytes(grid, geom, fwi.GRADIENT_WORKSPACE)
+    plane = cfg.NY * (-(-cfg.NX // 64) * 64) * 4
+    assert none < ck < hist
+    assert hist >= (cfg.nt + 1) * plane
+    assert grad >= ck + 2 * cfg.nshots * cfg.nt * cfg.nrec * 4
+    K = fwi.checkpoint_interval(grid, geom)
+    assert 1 <= K <= cfg.nt
+    assert abs(K - math.sqrt(3 * cfg.nt)) < 0.15 * math.sqrt(3 * cfg.nt)
+    for v in (none, ck, hist, grad):
+        assert v % 256 == 0
+
+
+def test_workspace_large_config_fits_hbm():
+    cfg = I.config_large()
+    src, rec = I.geometry(cfg)
+    grid = fwi.grid_from_config(cfg)
+    geom = fwi.Geometry(src, rec, FAKE)
+    grad = fwi.workspace_bytes(grid, geom, fwi.GRADIENT_WORKSPACE)
+    assert grad < 200e9, grad / 1e9   # fits in 288 GB with room for the caller
+
+
+def _status_forward(grid, geom, ws_bytes=None, save=fwi.FWI_SAVE_NONE, ptrs=(FAKE, FAKE, FAKE),
+                    ws_addr=FAKE):
+    if ws_bytes is None:
+        ws_bytes = 0
+    return fwi.fdtd_forward(grid, geom, ptrs[0], ptrs[1], ptrs[2], save, (ws_addr, ws_bytes),
+                            stream=0, raise_on_error=False)
+
+
+def test_forward_rejects_small_or_misaligned_workspace():
+    _, grid, geom = _tiny()
+    need = fwi.workspace_bytes(grid, geom, fwi.FWI_SAVE_NONE)
+    assert _status_forward(grid, geom, need - 1) == fwi.FWI_ENOMEM
+    assert _status_forward(grid, geom, need, ws_addr=FAKE + 4) == fwi.FWI_ENOMEM
+    assert _status_forward(grid, geom, need, ws_addr=0) == fwi.FWI_ENOMEM
+
+
+def test_forward_rejects_null_pointers_and_bad_mode():
+    _, grid, geom = _tiny()
+    assert _status_forward(grid, geom, 0, ptrs=(0, FAKE, FAKE)) == fwi.FWI_EINVAL
+    assert _status_forward(grid, geom, 0, ptrs=(FAKE, 0, FAKE)) == fwi.FWI_EINVAL
+    assert _status_forward(grid, geom, 0, ptrs=(FAKE, FAKE, 0)) == fwi.FWI_EINVAL
+    assert _status_forward(grid, geom, 0, save=7) == fwi.FWI_EINVAL
+    g2 = fwi.Geometry(geom.src, geom.rec, None)   # NULL wavelet
+    assert _status_forward(grid, g2, 0) == fwi.FWI_EINVAL
+
+
+def test_cfl_bound():
+    cfg, grid, geom = _tiny()
+    bound = 1.0 / (I.C0 * math.sqrt(1 / cfg.dx ** 2 + 1 / cfg.dy ** 2))
+    grid.dt = bound * 1.001
+    assert _status_forward(grid, geom) == fwi.FWI_ECFL
+    out = ctypes.c_size_t()
+    assert fwi.lib().fwi_workspace_bytes(ctypes.byref(grid), ctypes.byref(geom.c), 0,
+                                         ctypes.byref(out)) == fwi.FWI_ECFL
+    grid.dt = bound          # exactly at the bound is allowed
+    assert _status_forward(grid, geom) == fwi.FWI_ENOMEM
+
+
+@pytest.mark.parametrize("field,value", [("nx", 0), ("ny", -1), ("npml", -1), ("nt", 0),
+                                         ("dx", 0.0), ("dy", float("nan")), ("dt", -1e-12),
+                                         ("cpml_order", 0), ("cpml_order", 17),
+                                         ("cpml_sigma_scale", -1.0), ("cpml_kappa_max", 0.5),
+                                         ("cpml_alpha_max", float("inf"))])
+def test_grid_parameter_checks(field, value):
+    _, grid, geom = _tiny()
+    setattr(grid, field, value)
+    assert _status_forward(grid, geom) == fwi.FWI_EINVAL
+
+
+def test_geometry_checks():
+    cfg, grid, geom = _tiny()
+    p = cfg.npml
+    bad_src = geom.src.copy()
+    bad_src[0] = (p - 1, p + 1)               # inside the CPML
+    assert _status_forward(grid, fwi.Geometry(bad_src, geom.rec, FAKE)) == fwi.FWI_EGEOM
+    bad_rec = geom.rec.copy()
+    bad_rec[0, 5] = (p + 3, cfg.NY - p)       # below the interior
+    assert _status_forward(grid, fwi.Geometry(geom.src, bad_rec, FAKE)) == fwi.FWI_EGEOM
+    # npml = 0: the PEC ring is excluded even though it is "interior"
+    g0 = fwi.make_grid(20, 20, 0, 10, 0.01, 0.01, 1e-11)
+    ring = fwi.Geometry(np.array([[0, 5]]), np.array([[[5, 5]]]), FAKE)
+    assert _status_forward(g0, ring) == fwi.FWI_EGEOM
+    ok = fwi.Geometry(np.array([[1, 5]]), np.array([[[18, 18]]]), FAKE)
+    assert _status_forward(g0, ok) == fwi.FWI_ENOMEM
+    # zero receivers / shots
+    none = fwi.Geometry(geom.src, np.zeros((1, 0, 2), np.int32), FAKE)
+    assert _status_forward(grid, none) == fwi.FWI_EINVAL
+
+
+def test_adjoint_and_gradient_argument_checks():
+    _, grid, geom = _tiny()
+    L = fwi.lib()
+    ws = (FAKE, 0)
+    for mode in (fwi.FWI_SAVE_NONE, 5):
+        st = fwi.fdtd_adjoint(grid, geom, FAKE, FAKE, FAKE, FAKE, FAKE, None, mode, ws,
+                              stream=0, raise_on_error=False)
+        assert st == fwi.FWI_EINVAL
+    st = fwi.fdtd_adjoint(grid, geom, FAKE, FAKE, None, FAKE, FAKE, None,
+                          fwi.FWI_SAVE_CHECKPOINT, ws, stream=0, raise_on_error=False)
+    assert st == fwi.FWI_EINVAL
+    st = fwi.fdtd_adjoint(grid, geom, FAKE, FAKE, FAKE, FAKE, FAKE, None,
+                          fwi.FWI_SAVE_CHECKPOINT, ws, stream=0, raise_on_error=False)
+    assert st == fwi.FWI_ENOMEM
+    st = fwi.fwi_gradient(grid, geom, FAKE, FAKE, FAKE, None, FAKE, FAKE, None, ws,
+                          stream=0, raise_on_error=False)
+    assert st == fwi.FWI_EINVAL
+    st = fwi.fwi_gradient(grid, geom, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None, ws,
+                          stream=0, raise_on_error=False)
+    assert st == fwi.FWI_ENOMEM
+    assert L.fwi_workspace_bytes(ctypes.byref(grid), ctypes.byref(geom.c), 0, None) == fwi.FWI_EINVAL
+    assert L.fwi_workspace_bytes(None, ctypes.byref(geom.c), 0,
+                                 ctypes.byref(ctypes.c_size_t())) == fwi.FWI_EINVAL
