@@ -33,12 +33,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kernel: str, cells: int, shots: int) -> float:
-    """Bytes one launch must move by the method itself: a forward cell-update
-    reads and writes Ez, Hx, Hy (24 B); the adjoint also needs the forward
-    Ez^n (28 B).  Ca and Cs (8 B per cell) are shared by all shots."""
-    per = {"k_fwd_step": 24.0, "k_adj_step": 28.0}[kernel]
-    return cells * (per * shots + 8.0)
+# Per-step algorithmic bytes of each stencil kernel for one cell and all its
+# shots: a forward cell-update reads and writes Ez, Hx, Hy (24 B); the
+# adjoint one reads and writes the three adjoint fields and reads the forward
+# Ez^n (28 B); Ca and Cs (8 B per cell) are shared by all shots.  One launch
+# advances several time levels; a gradient runs 2 nt forward levels (forward
+# sweep and checkpoint re-forward) and nt adjoint levels.
+PER_CELL_UPDATE = {"k_fwd_lean": 24.0, "k_fwd_stream": 24.0,
+                   "k_adj_lean": 28.0, "k_adj_stream": 28.0}
+
+
+def algorithmic_bytes(kernel: str, cell_updates: float, shots: int) -> float:
+    """Algorithmic bytes for `cell_updates` cell x shot x step updates."""
+    return cell_updates * (PER_CELL_UPDATE[kernel] + 8.0 / shots)
 
 
 def cpu_baseline(cfg, e0, s0, src, rec, w, steps: int):
@@ -76,7 +83,12 @@ def main():
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--sample-every", type=int, default=8,
                     help="time every k-th launch of each hot kernel with HIP events")
-    ap.add_argument("--cpu-steps", type=int, default=600)
+    ap.add_argument("--cpu-steps", type=int, default=2400)
+    ap.add_argument("--nt", type=int, default=None,
+                    help="override the number of time steps (short profiler runs)")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB "
+                         "(calibrates the profiler's HBM byte counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -95,7 +107,18 @@ def main():
     fwi.lib()
 
     cfg = WORKLOADS[args.workload]()
+    if args.nt is not None:
+        cfg = cfg.with_(nt=args.nt)
     dev = "cuda"
+    if args.copy_probe_mb > 0:
+        n = args.copy_probe_mb * (1 << 20) // 4
+        a = torch.ones(n, device=dev)
+        b = torch.empty(n, device=dev)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"bench: copy probe {args.copy_probe_mb} MiB done")
+        del a, b
     log(f"bench: workload {cfg.name} NX={cfg.NX} NY={cfg.NY} nt={cfg.nt} shots={cfg.nshots} "
         f"receivers={cfg.nrec}")
     e, s, e0, s0 = I.model_for(cfg)
@@ -135,10 +158,11 @@ def main():
         tm = fwi.fwi_timing(sample_every=args.sample_every)
         fwi.fwi_gradient_timed(grid, geom, e0t, s0t, obs, mis, ge, gs, None, ws, tm)
         for name, v in tm.as_dict().items():
-            a = kt.setdefault(name, {"launches": 0, "timed": 0, "ms": 0.0})
+            a = kt.setdefault(name, {"launches": 0, "timed": 0, "ms": 0.0, "updates": 0.0})
             a["launches"] += v["launches"]
             a["timed"] += v["timed"]
             a["ms"] += v["avg_ms"] * v["timed"]
+            a["updates"] += v["cell_updates"]
         log(f"bench: step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
@@ -149,18 +173,18 @@ def main():
     value = updates / (ms_per_step / 1e3) / 1e9
     kernels = {}
     for name, a in kt.items():
+        if a["launches"] == 0:
+            continue
         avg = a["ms"] / a["timed"] if a["timed"] else 0.0
+        kb = algorithmic_bytes(name, a["updates"], S) / a["launches"]
         kernels[name] = {"launches_per_step": a["launches"] // args.steps,
                          "avg_ms": avg,
-                         "ms_per_step": avg * a["launches"] / args.steps}
-    dom = max((k for k in kernels if k in ("k_fwd_step", "k_adj_step")),
-              key=lambda k: kernels[k]["ms_per_step"])
-    by = algorithmic_bytes(dom, cells, S)
-    achieved = by / (kernels[dom]["avg_ms"] / 1e3) / 1e9
-    for name in kernels:
-        if name in ("k_fwd_step", "k_adj_step"):
-            kernels[name]["algorithmic_GBps"] = (algorithmic_bytes(name, cells, S)
-                                                 / (kernels[name]["avg_ms"] / 1e3) / 1e9)
+                         "ms_per_step": avg * a["launches"] / args.steps,
+                         "bytes_per_launch": kb,
+                         "algorithmic_GBps": kb / (avg / 1e3) / 1e9 if avg > 0 else None}
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    by = kernels[dom]["bytes_per_launch"]
+    achieved = kernels[dom]["algorithmic_GBps"]
     # algorithmic bytes of the whole step (forward + adjoint, one pass each)
     alg_step = cells * nt * (S * (24.0 + 28.0) + 16.0)
     out = {

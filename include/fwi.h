@@ -169,6 +169,9 @@ typedef struct fwi_kernel_time {
     int32_t launches;          /* launches of this kernel during the call     */
     int32_t timed;             /* launches bracketed by events                */
     double avg_ms;             /* mean duration of the timed launches         */
+    double cell_updates;       /* cells x shots x time steps these launches
+                                  computed (cells each wave owns; halos and
+                                  recomputation not counted)                  */
 } fwi_kernel_time;
 typedef struct fwi_timing {
     int32_t sample_every;      /* in: >= 1                                   */

@@ -80,13 +80,58 @@ int make_dims(const fwi_grid *grid, const fwi_geom *geom, Dims &d) {
     return check_geom(geom, d);
 }
 
-// Checkpoint interval minimising checkpoints + segment buffer:
-// ceil(nt/K) * C + (K+1) * E with C one full state and E one Ez slot.
+// Checkpoint interval minimising checkpoints + segment buffer,
+// ceil(nt/K) * C + (K+1) * E with C one full state and E one Ez slot, rounded
+// to a multiple of the streaming depth so segments split into full passes.
 int choose_k(const Dims &d) {
     const double C = 3.0 * d.plane + 2.0 * d.xs + 2.0 * d.ys;
     const double E = (double)d.plane;
-    int K = (int)std::lround(std::sqrt((double)d.nt * C / E));
+    const double k = std::sqrt((double)d.nt * C / E);
+    int K = (int)std::lround(k / kStreamK) * kStreamK;
+    K = std::max(K, kStreamK);
     return std::max(1, std::min(K, d.nt));
+}
+
+// Streaming decomposition: x strips of 64 - 2K output columns and row bands.
+// The lean sub-grid is the set of strips and bands whose whole footprint
+// (K halo columns on each side, K rows above and below) avoids the CPML strips
+// and the outside of the grid: columns [npml, NX-2-npml], rows
+// [npml, NY-2-npml].  Bands: a top band [0, npml+K), interior bands, a bottom
+// band [NY-1-npml-K, NY); without a lean sub-grid, plain bands.
+void make_tiling(const Dims &d, Layout &L) {
+    constexpr int K = kStreamK, OW = 64 - 2 * K;
+    const int target_waves = 4096;   // about four waves per SIMD
+    const int max_bands = (int)(sizeof(L.bands) / sizeof(int)) - 1;
+    L.nstrip = (d.NX + OW - 1) / OW;
+    // strip k is lean iff k*OW - K >= npml and k*OW - K + 63 <= NX - 2 - npml
+    int s0 = (d.npml + K + OW - 1) / OW;
+    const int hi = d.NX - 2 - d.npml - 63 + K;
+    int s1 = hi >= 0 ? hi / OW + 1 : 0;
+    const int yA = d.npml + K, yB = d.NY - 1 - d.npml - K;
+    int nb = 0;
+    auto split = [&](int lo, int hi_, int parts) {
+        const int h = (hi_ - lo + parts - 1) / parts;
+        for (int y = lo; y < hi_; y += h) L.bands[nb++] = y;
+    };
+    if (s1 > s0 && yB - yA >= 4 * K) {
+        const int nls = s1 - s0;
+        int parts = (target_waves + d.S * nls - 1) / (d.S * nls);
+        parts = std::max(1, std::min(parts, std::min((yB - yA) / (4 * K), max_bands - 2)));
+        L.bands[nb++] = 0;
+        split(yA, yB, parts);
+        L.lean_b0 = 1;
+        L.lean_b1 = nb;
+        L.bands[nb++] = yB;
+        L.lean_s0 = s0;
+        L.lean_s1 = s1;
+    } else {
+        int parts = (target_waves + d.S * L.nstrip - 1) / (d.S * L.nstrip);
+        parts = std::max(1, std::min(parts, std::min(d.NY / (4 * K) + 1, max_bands)));
+        split(0, d.NY, parts);
+        L.lean_s0 = L.lean_s1 = L.lean_b0 = L.lean_b1 = 0;
+    }
+    L.nband = nb;
+    L.bands[nb] = d.NY;
 }
 
 // Workspace layout for a mode (FWI_SAVE_* or -1 = fwi_gradient).
@@ -109,9 +154,11 @@ int make_layout(const Dims &d, int mode, Layout &L) {
     L.off_Cs = take(d.plane * sizeof(float));
     L.off_prof = take((size_t)6 * (d.NX + d.NY) * sizeof(float));
     L.off_src = take(S * 2 * sizeof(int));
-    L.off_rec = take(S * d.R * 2 * sizeof(int));
-    L.off_rord = take(S * d.R * sizeof(int));
-    L.off_rlen = take(S * d.R * sizeof(int));
+    L.off_rrow = take(S * (d.NY + 1) * sizeof(int));
+    L.off_rcol = take(S * d.R * sizeof(int));
+    L.off_ridx = take(S * d.R * sizeof(int));
+    L.off_rspan = take(S * 2 * sizeof(int));
+    L.off_bands = take(sizeof(L.bands));
     L.state_bytes = align_up(field) * 2 + align_up(xs) * 2 + align_up(ys) * 2;
     L.off_fwd[0] = take(L.state_bytes);
     L.off_fwd[1] = take(L.state_bytes);
@@ -138,8 +185,8 @@ int make_layout(const Dims &d, int mode, Layout &L) {
     if (mode != FWI_SAVE_NONE) {
         L.off_adj[0] = take(align_up(field) + L.state_bytes);
         L.off_adj[1] = take(align_up(field) + L.state_bytes);
-        L.off_S1 = take(d.plane * sizeof(float));
-        L.off_S2 = take(d.plane * sizeof(float));
+        L.off_S1 = take(field);
+        L.off_S2 = take(field);
     }
     L.off_res = L.off_trc = L.off_mis = 0;
     if (mode == -1) {
@@ -149,6 +196,7 @@ int make_layout(const Dims &d, int mode, Layout &L) {
         L.off_mis = take(kMisfitBlocks * sizeof(double));
     }
     L.total = off;
+    make_tiling(d, L);
     return FWI_OK;
 }
 
@@ -202,20 +250,23 @@ struct Ptrs {
     } while (0)
 
 // Optional per-kernel timing with HIP events on the call's stream.
-enum Kind { K_FWD = 0, K_ADJ = 1, K_INJ = 2, K_NKINDS = 3 };
-const char *const kKindName[K_NKINDS] = {"k_fwd_step", "k_adj_step", "k_adj_inject"};
+enum Kind { K_FWD_LEAN = 0, K_FWD = 1, K_ADJ_LEAN = 2, K_ADJ = 3, K_NKINDS = 4 };
+const char *const kKindName[K_NKINDS] = {"k_fwd_lean", "k_fwd_stream", "k_adj_lean",
+                                         "k_adj_stream"};
 
 struct Timer {
     fwi_timing *t = nullptr;
     hipStream_t st = nullptr;
-    int launches[K_NKINDS] = {0, 0, 0};
+    int launches[K_NKINDS] = {0, 0, 0, 0};
+    double updates[K_NKINDS] = {0, 0, 0, 0};
     struct Rec { int kind; hipEvent_t a, b; };
     std::vector<Rec> recs;
     bool failed = false;
 
     // Launch `fn` (returning hipError_t), bracketed by events when sampled.
     template <class F>
-    hipError_t run(int kind, F fn) {
+    hipError_t run(int kind, double cell_updates, F fn) {
+        updates[kind] += cell_updates;
         const int idx = launches[kind]++;
         if (!t || idx % t->sample_every != 0 || failed) return fn();
         Rec r{kind, nullptr, nullptr};
@@ -234,8 +285,8 @@ struct Timer {
 
     int finish() {
         if (!t) return FWI_OK;
-        double sum[K_NKINDS] = {0, 0, 0};
-        int cnt[K_NKINDS] = {0, 0, 0};
+        double sum[K_NKINDS] = {0, 0, 0, 0};
+        int cnt[K_NKINDS] = {0, 0, 0, 0};
         int rc = FWI_OK;
         if (hipStreamSynchronize(st) != hipSuccess) rc = FWI_EHIP;
         for (auto &r : recs) {
@@ -256,41 +307,49 @@ struct Timer {
             o.launches = launches[k];
             o.timed = cnt[k];
             o.avg_ms = cnt[k] ? sum[k] / cnt[k] : 0.0;
+            o.cell_updates = updates[k];
         }
         return rc;
     }
 };
 
-// Geometry to the device, plus receivers grouped by cell for the adjoint
-// source (sorted by cell, stable in receiver index).
+// Geometry to the device: sources, and per shot the receivers sorted by
+// (row, column) - stable in receiver index, so receivers sharing a cell stay
+// in index order - with a row CSR.
 int upload_geometry(const Ptrs &P, const fwi_geom *g, hipStream_t st) {
     const Dims &d = P.L->d;
-    const size_t S = d.S, R = d.R;
-    std::vector<int> order(S * R), glen(S * R, 0);
+    const size_t S = d.S, R = d.R, NY = d.NY;
+    std::vector<int> rrow(S * (NY + 1)), rcol(S * R), ridx(S * R), rspan(S * 2);
     for (size_t s = 0; s < S; ++s) {
         const int32_t *rc = g->rec_ij + 2 * s * R;
-        int *o = order.data() + s * R;
+        int *o = ridx.data() + s * R;
         std::iota(o, o + R, 0);
         std::stable_sort(o, o + R, [&](int a, int b) {
             const int64_t ka = (int64_t)rc[2 * a + 1] * d.NX + rc[2 * a];
             const int64_t kb = (int64_t)rc[2 * b + 1] * d.NX + rc[2 * b];
             return ka < kb;
         });
-        size_t p = 0;
-        while (p < R) {
-            size_t q = p + 1;
-            while (q < R && rc[2 * o[q]] == rc[2 * o[p]] && rc[2 * o[q] + 1] == rc[2 * o[p] + 1]) ++q;
-            glen[s * R + p] = (int)(q - p);
-            p = q;
+        int *rr = rrow.data() + s * (NY + 1);
+        size_t q = 0;
+        for (size_t j = 0; j <= NY; ++j) {
+            while (q < R && (size_t)rc[2 * o[q] + 1] < j) ++q;
+            rr[j] = (int)q;
         }
+        for (size_t k = 0; k < R; ++k) rcol[s * R + k] = rc[2 * o[k]];
+        rspan[2 * s] = rc[2 * o[0] + 1];
+        rspan[2 * s + 1] = rc[2 * o[R - 1] + 1];
     }
     FWI_TRY(hipMemcpyAsync(P.i(P.L->off_src), g->src_ij, S * 2 * sizeof(int),
                            hipMemcpyHostToDevice, st));
-    FWI_TRY(hipMemcpyAsync(P.i(P.L->off_rec), g->rec_ij, S * R * 2 * sizeof(int),
+    FWI_TRY(hipMemcpyAsync(P.i(P.L->off_rrow), rrow.data(), rrow.size() * sizeof(int),
                            hipMemcpyHostToDevice, st));
-    FWI_TRY(hipMemcpyAsync(P.i(P.L->off_rord), order.data(), S * R * sizeof(int),
+    FWI_TRY(hipMemcpyAsync(P.i(P.L->off_rcol), rcol.data(), rcol.size() * sizeof(int),
                            hipMemcpyHostToDevice, st));
-    FWI_TRY(hipMemcpyAsync(P.i(P.L->off_rlen), glen.data(), S * R * sizeof(int),
+    FWI_TRY(hipMemcpyAsync(P.i(P.L->off_ridx), ridx.data(), ridx.size() * sizeof(int),
+                           hipMemcpyHostToDevice, st));
+    FWI_TRY(hipMemcpyAsync(P.i(P.L->off_rspan), rspan.data(), rspan.size() * sizeof(int),
+                           hipMemcpyHostToDevice, st));
+    FWI_TRY(hipMemcpyAsync(P.i(P.L->off_bands), P.L->bands, sizeof(P.L->bands),
                            hipMemcpyHostToDevice, st));
     // pageable host sources: make sure the copies consumed them before the
     // vectors go out of scope
@@ -322,27 +381,61 @@ int copy_state(const State &dst, const State &src, const Dims &d, hipStream_t st
     return FWI_OK;
 }
 
-FwdStepArgs fwd_args(const Ptrs &P, const fwi_geom *g) {
-    const Dims &d = P.L->d;
-    FwdStepArgs a;
+Tiling tiling(const Ptrs &P) {
+    const Layout &L = *P.L;
+    Tiling t;
+    t.bands = P.i(L.off_bands);
+    t.nstrip = L.nstrip;
+    t.nband = L.nband;
+    t.lean_s0 = L.lean_s0; t.lean_s1 = L.lean_s1;
+    t.lean_b0 = L.lean_b0; t.lean_b1 = L.lean_b1;
+    return t;
+}
+
+// Cells owned by the lean sub-grid (all of its columns and rows are inside
+// the grid by construction).
+double lean_cells(const Layout &L) {
+    if (L.lean_s1 <= L.lean_s0) return 0.0;
+    const int OW = 64 - 2 * kStreamK;
+    return (double)(L.lean_s1 - L.lean_s0) * OW *
+           (double)(L.bands[L.lean_b1] - L.bands[L.lean_b0]);
+}
+
+StreamGeom stream_geom(const Ptrs &P, const fwi_geom *g) {
+    StreamGeom sg;
+    sg.src_ij = P.i(P.L->off_src);
+    sg.wavelet = g->wavelet;
+    sg.rrow = P.i(P.L->off_rrow);
+    sg.rcol = P.i(P.L->off_rcol);
+    sg.ridx = P.i(P.L->off_ridx);
+    sg.rspan = P.i(P.L->off_rspan);
+    return sg;
+}
+
+FwdStreamArgs fwd_args(const Ptrs &P, const fwi_geom *g) {
+    const Layout &L = *P.L;
+    const Dims &d = L.d;
+    FwdStreamArgs a;
     a.NX = d.NX; a.NY = d.NY; a.npml = d.npml; a.pitch = d.pitch;
-    a.W = d.W; a.Hs = d.Hs; a.S = d.S; a.R = d.R; a.nt = d.nt; a.n = 0;
+    a.W = d.W; a.Hs = d.Hs; a.S = d.S; a.R = d.R; a.nt = d.nt;
+    a.n = 0; a.nlev = 0;
+    a.tl = tiling(P);
     a.plane = d.plane; a.xs = d.xs; a.ys = d.ys;
+    a.lev_stride = (size_t)d.S * d.plane;
+    a.ch = (float)(d.dt / kMu0);
     a.rdx = (float)(1.0 / d.dx);
     a.rdy = (float)(1.0 / d.dy);
-    a.ch = (float)(d.dt / kMu0);
     a.src_scale = (float)(1.0 / (d.dx * d.dy));
-    a.Ca = P.f(P.L->off_Ca);
-    a.Cs = P.f(P.L->off_Cs);
+    a.Ca = P.f(L.off_Ca);
+    a.Cs = P.f(L.off_Cs);
     a.p = P.prof();
-    a.g.src_ij = P.i(P.L->off_src);
-    a.g.wavelet = g->wavelet;
-    a.g.rec_ij = P.i(P.L->off_rec);
-    a.g.traces = nullptr;
+    a.E_in = nullptr; a.E_out = nullptr; a.E_lev = nullptr;
+    a.traces = nullptr;
+    a.g = stream_geom(P, g);
     return a;
 }
 
-// Coefficients, profiles, geometry; forward state cleared.
+// Coefficients, profiles, geometry.
 int setup(const Ptrs &P, const fwi_geom *g, const float *eps_r, const float *sigma,
           hipStream_t st) {
     const Dims &d = P.L->d;
@@ -354,21 +447,35 @@ int setup(const Ptrs &P, const fwi_geom *g, const float *eps_r, const float *sig
     return FWI_OK;
 }
 
-// Run forward steps [n0, n1).  E of step n is read from ein(n) and written
-// to eout(n); the H / CPML state ping-pongs between fwd[0] and fwd[1]
-// starting at fwd[cur].  Returns the index of the state holding the result.
-template <class EIn, class EOut>
-int forward_steps(const Ptrs &P, FwdStepArgs a, int n0, int n1, int &cur, EIn ein,
-                  EOut eout, float *traces, hipStream_t st, Timer &tm) {
-    State fs[2] = {P.state(P.L->off_fwd[0], false), P.state(P.L->off_fwd[1], false)};
-    a.g.traces = traces;
-    for (int n = n0; n < n1; ++n) {
+// Forward steps [n0, n1) in passes of up to kStreamK steps.  E of the pass
+// starting at n is read from ein(n); per-level E goes to elev(n) (history /
+// segment) or, when elev returns null, the final E of the pass to eout(n).
+// The H / CPML state ping-pongs between fwd[cur] and fwd[cur ^ 1].
+template <class EIn, class EOut, class ELev>
+int forward_passes(const Ptrs &P, FwdStreamArgs a, int n0, int n1, int &cur, EIn ein,
+                   EOut eout, ELev elev, float *traces, hipStream_t st, Timer &tm) {
+    const Layout &L = *P.L;
+    State fs[2] = {P.state(L.off_fwd[0], false), P.state(L.off_fwd[1], false)};
+    a.traces = traces;
+    const double all = (double)L.d.NX * L.d.NY * L.d.S;
+    const double lean = lean_cells(L) * L.d.S;
+    const Tiling full = a.tl;
+    for (int n = n0; n < n1; n += kStreamK) {
         a.n = n;
+        a.nlev = std::min(kStreamK, n1 - n);
         a.E_in = ein(n);
-        a.E_out = eout(n);
+        a.E_lev = elev(n);
+        a.E_out = a.E_lev ? nullptr : eout(n);
         a.in = fs[cur];
         a.out = fs[cur ^ 1];
-        FWI_TRY(tm.run(K_FWD, [&] { return launch_fwd_step(a, st); }));
+        // a pass shorter than K (end of the time axis) runs entirely in the
+        // general kernel
+        a.tl = full;
+        if (a.nlev < kStreamK) a.tl.lean_s0 = a.tl.lean_s1 = 0;
+        const double ln = a.tl.lean_s1 > a.tl.lean_s0 ? lean : 0.0;
+        if (ln > 0)
+            FWI_TRY(tm.run(K_FWD_LEAN, ln * a.nlev, [&] { return launch_fwd_lean(a, st); }));
+        FWI_TRY(tm.run(K_FWD, (all - ln) * a.nlev, [&] { return launch_fwd_stream(a, st); }));
         cur ^= 1;
     }
     return FWI_OK;
@@ -385,29 +492,36 @@ int do_forward(const Layout &L, const fwi_geom *g, const float *eps_r,
     rc = zero_state(fs0, d, false, st);
     if (rc != FWI_OK) return rc;
     FWI_TRY(launch_fill(P.slot(0), (size_t)d.S * d.plane, 0.f, st));
-    FwdStepArgs a = fwd_args(P, g);
+    FwdStreamArgs a = fwd_args(P, g);
     int cur = 0;
     if (L.mode == FWI_SAVE_HISTORY) {
-        return forward_steps(
+        return forward_passes(
             P, a, 0, d.nt, cur, [&](int n) { return P.slot(n); },
-            [&](int n) { return P.slot(n + 1); }, traces, st, tm);
+            [&](int) { return (float *)nullptr; }, [&](int n) { return P.slot(n + 1); },
+            traces, st, tm);
     }
-    // ping-pong E between slots 0 and 1; checkpoint (E, H, psi) every K steps
-    const int K = L.mode == FWI_SAVE_CHECKPOINT || L.mode == -1 ? L.K : d.nt;
+    // E ping-pongs between slots 0 and 1 pass by pass; with checkpoints, the
+    // full state (E, H, CPML memories) is copied out every K steps
+    const int K = L.ncp > 0 ? L.K : d.nt;
+    int e = 0;
     for (int n0 = 0; n0 < d.nt; n0 += K) {
         const int n1 = std::min(d.nt, n0 + K);
         if (L.ncp > 0) {
             const int c = n0 / K;
             char *cp = static_cast<char *>(ws) + L.off_ckpt + (size_t)c * L.ckpt_stride;
             const size_t f = (size_t)d.S * d.plane * sizeof(float);
-            FWI_TRY(hipMemcpyAsync(cp, P.slot(n0 & 1), f, hipMemcpyDeviceToDevice, st));
+            FWI_TRY(hipMemcpyAsync(cp, P.slot(e), f, hipMemcpyDeviceToDevice, st));
             State cst = P.state(L.off_ckpt + (size_t)c * L.ckpt_stride + align_up(f), false);
             rc = copy_state(cst, P.state(L.off_fwd[cur], false), d, st);
             if (rc != FWI_OK) return rc;
         }
-        rc = forward_steps(
-            P, a, n0, n1, cur, [&](int n) { return P.slot(n & 1); },
-            [&](int n) { return P.slot((n + 1) & 1); }, traces, st, tm);
+        rc = forward_passes(
+            P, a, n0, n1, cur, [&](int) { return P.slot(e); },
+            [&](int) {
+                e ^= 1;
+                return P.slot(e);
+            },
+            [&](int) { return (float *)nullptr; }, traces, st, tm);
         if (rc != FWI_OK) return rc;
     }
     return FWI_OK;
@@ -422,51 +536,62 @@ int do_adjoint(const Layout &L, const fwi_geom *g, const float *eps_r,
     int rc = zero_state(as[0], d, true, st);
     if (rc != FWI_OK) return rc;
     float *S1 = P.f(L.off_S1), *S2 = P.f(L.off_S2);
-    FWI_TRY(launch_fill(S1, d.plane, 0.f, st));
-    FWI_TRY(launch_fill(S2, d.plane, 0.f, st));
+    const size_t field = (size_t)d.S * d.plane;
+    FWI_TRY(launch_fill(S1, field, 0.f, st));
+    FWI_TRY(launch_fill(S2, field, 0.f, st));
 
-    AdjStepArgs a;
+    AdjStreamArgs a;
     a.NX = d.NX; a.NY = d.NY; a.npml = d.npml; a.pitch = d.pitch;
     a.W = d.W; a.Hs = d.Hs; a.S = d.S; a.R = d.R; a.nt = d.nt;
+    a.tl = tiling(P);
     a.plane = d.plane; a.xs = d.xs; a.ys = d.ys;
+    a.lev_stride = field;
+    a.ch = (float)(d.dt / kMu0);
     a.rdx = (float)(1.0 / d.dx);
     a.rdy = (float)(1.0 / d.dy);
-    a.ch = (float)(d.dt / kMu0);
     a.src_scale = (float)(1.0 / (d.dx * d.dy));
     a.Ca = P.f(L.off_Ca);
     a.Cs = P.f(L.off_Cs);
     a.p = P.prof();
     a.S1 = S1;
     a.S2 = S2;
-    a.src_ij = P.i(L.off_src);
+    a.residual = residual;
     a.src_adjoint = src_adj;
+    a.src_ij = P.i(L.off_src);
+    a.g = stream_geom(P, g);
     int acur = 0;
-    auto adj_range = [&](int n_hi, int n_lo, auto eslot) -> int {
-        for (int n = n_hi - 1; n >= n_lo; --n) {
-            a.n = n;
-            a.E_np1 = eslot(n + 1);
-            a.E_n = eslot(n);
+    // adjoint passes over steps [n_lo, n_hi), the forward Ez^{n_lo + k} in slot k
+    const double all = (double)d.NX * d.NY * d.S;
+    const double lean = lean_cells(L) * d.S;
+    const Tiling full = a.tl;
+    auto adj_range = [&](int n_hi, int n_lo) -> int {
+        for (int n_top = n_hi; n_top > n_lo; n_top -= kStreamK) {
+            a.nlev = std::min(kStreamK, n_top - n_lo);
+            a.n_top = n_top;
+            a.n_base = n_lo;
+            a.E_top = P.slot(n_top - n_lo);
+            a.E_lev = P.slot(0);
             a.in = as[acur];
             a.out = as[acur ^ 1];
-            FWI_TRY(tm.run(K_ADJ, [&] { return launch_adj_step(a, st); }));
-            FWI_TRY(tm.run(K_INJ, [&] {
-                return launch_adj_inject(residual, as[acur ^ 1].E, P.i(L.off_rec),
-                                         P.i(L.off_rord), P.i(L.off_rlen), d.S, d.R,
-                                         d.nt, n, d.plane, d.pitch, st);
-            }));
+            a.tl = full;
+            if (a.nlev < kStreamK) a.tl.lean_s0 = a.tl.lean_s1 = 0;
+            const double ln = a.tl.lean_s1 > a.tl.lean_s0 ? lean : 0.0;
+            if (ln > 0)
+                FWI_TRY(tm.run(K_ADJ_LEAN, ln * a.nlev, [&] { return launch_adj_lean(a, st); }));
+            FWI_TRY(tm.run(K_ADJ, (all - ln) * a.nlev, [&] { return launch_adj_stream(a, st); }));
             acur ^= 1;
         }
         return FWI_OK;
     };
 
     if (L.mode == FWI_SAVE_HISTORY) {
-        rc = adj_range(d.nt, 0, [&](int n) { return P.slot(n); });
+        rc = adj_range(d.nt, 0);
         if (rc != FWI_OK) return rc;
     } else {
         // segment by segment, last first: restore the checkpoint, re-run the
         // segment forward into slots 0..K, then run the adjoint through it
-        FwdStepArgs fa = fwd_args(P, g);
-        const size_t f = (size_t)d.S * d.plane * sizeof(float);
+        FwdStreamArgs fa = fwd_args(P, g);
+        const size_t f = field * sizeof(float);
         for (int c = L.ncp - 1; c >= 0; --c) {
             const int n0 = c * L.K, n1 = std::min(d.nt, n0 + L.K);
             const size_t co = L.off_ckpt + (size_t)c * L.ckpt_stride;
@@ -474,16 +599,17 @@ int do_adjoint(const Layout &L, const fwi_geom *g, const float *eps_r,
             rc = copy_state(P.state(L.off_fwd[0], false), P.state(co + align_up(f), false), d, st);
             if (rc != FWI_OK) return rc;
             int cur = 0;
-            rc = forward_steps(
+            rc = forward_passes(
                 P, fa, n0, n1, cur, [&](int n) { return P.slot(n - n0); },
+                [&](int) { return (float *)nullptr; },
                 [&](int n) { return P.slot(n + 1 - n0); }, nullptr, st, tm);
             if (rc != FWI_OK) return rc;
-            rc = adj_range(n1, n0, [&](int n) { return P.slot(n - n0); });
+            rc = adj_range(n1, n0);
             if (rc != FWI_OK) return rc;
         }
     }
-    FWI_TRY(launch_gradient_finalize(eps_r, sigma, S1, S2, g_eps, g_sig, d.NX, d.NY,
-                                     d.pitch, d.dt, st));
+    FWI_TRY(launch_gradient_finalize(eps_r, sigma, S1, S2, d.S, d.plane, g_eps, g_sig,
+                                     d.NX, d.NY, d.pitch, d.dt, st));
     return FWI_OK;
 }
 

@@ -60,13 +60,16 @@ struct Layout {
     int K;             // checkpoint interval (checkpoint modes)
     int ncp;           // number of checkpoints
     int nslots;        // Ez slots
+    // streaming decomposition (see Tiling)
+    int nstrip, nband, lean_s0, lean_s1, lean_b0, lean_b1;
+    int bands[64];
     size_t off_Ca, off_Cs, off_prof;
-    size_t off_src, off_rec, off_rord, off_rlen;
+    size_t off_src, off_rrow, off_rcol, off_ridx, off_rspan, off_bands;
     size_t off_fwd[2];
     size_t off_slots;
     size_t off_ckpt, ckpt_stride;
     size_t off_adj[2];
-    size_t off_S1, off_S2;
+    size_t off_S1, off_S2;    // per-shot [S][NY][pitch]
     size_t off_res, off_trc, off_mis;
     size_t state_bytes;   // one forward State (without E)
     size_t total;
@@ -74,58 +77,84 @@ struct Layout {
 
 // ---- kernel argument blocks -------------------------------------------------
 
-struct StepGeom {
-    const int *src_ij;        // device [S][2]
-    const float *wavelet;     // device [S][nt]
-    const int *rec_ij;        // device [S][R][2]
-    float *traces;            // device [S][nt][R] or null (no recording)
+// Time levels advanced per pass of the streaming kernels.
+constexpr int kStreamK = 8;
+
+// Source and receiver tables on the device.  Receivers of each shot are
+// sorted by (row, column), stable in receiver index; rrow is the row CSR.
+struct StreamGeom {
+    const int *src_ij;        // [S][2]
+    const float *wavelet;     // [S][nt]
+    const int *rrow;          // [S][NY+1]
+    const int *rcol;          // [S][R] column of the q-th receiver in that order
+    const int *ridx;          // [S][R] its receiver index
+    const int *rspan;         // [S][2] first and last receiver row
 };
 
-struct FwdStepArgs {
-    int NX, NY, npml, pitch, W, Hs, S, R, nt, n;
-    size_t plane, xs, ys;
-    float rdx, rdy, ch, src_scale;
-    const float *Ca, *Cs;
-    Profiles p;
-    const float *E_in;
-    float *E_out;
-    State in, out;
-    StepGeom g;
+// Row bands and the "lean" sub-grid.  bands[b] .. bands[b+1] are the rows a
+// wave of band b owns.  Waves with strip in [lean_s0, lean_s1) and band in
+// [lean_b0, lean_b1) touch no CPML cell and no cell outside the grid (their
+// whole footprint, halo included); they run the lean kernels and the general
+// kernels skip them.
+struct Tiling {
+    const int *bands;         // [nband + 1]
+    int nstrip, nband;
+    int lean_s0, lean_s1, lean_b0, lean_b1;
 };
 
-struct AdjStepArgs {
-    int NX, NY, npml, pitch, W, Hs, S, R, nt, n;
-    size_t plane, xs, ys;
-    float rdx, rdy, ch, src_scale;
+struct FwdStreamArgs {
+    int NX, NY, npml, pitch, W, Hs, S, R, nt;
+    int n, nlev;              // first step of the pass, steps in the pass (<= K)
+    Tiling tl;
+    size_t plane, xs, ys, lev_stride;
+    float ch, rdx, rdy, src_scale;
     const float *Ca, *Cs;
     Profiles p;
-    const float *E_np1;       // forward Ez^{n+1}, all shots
-    const float *E_n;         // forward Ez^n
-    State in, out;            // adjoint state lambda^{n+1} -> lambda^n
-    float *S1, *S2;           // [NY][pitch] correlation accumulators
-    const int *src_ij;
+    const float *E_in;        // Ez^n, all shots
+    float *E_out;             // Ez^{n+nlev} (unused when E_lev is set)
+    float *E_lev;             // or null: Ez^{n+l+1} to E_lev + l * lev_stride
+    State in, out;            // H and CPML memories, n-1/2 -> n+nlev-1/2
+    float *traces;            // [S][nt][R] or null
+    StreamGeom g;
+};
+
+struct AdjStreamArgs {
+    int NX, NY, npml, pitch, W, Hs, S, R, nt;
+    int n_top, n_base, nlev;  // pass covers steps n_top-1 .. n_top-nlev
+    Tiling tl;
+    size_t plane, xs, ys, lev_stride;
+    float ch, rdx, rdy, src_scale;
+    const float *Ca, *Cs;
+    Profiles p;
+    const float *E_top;       // forward Ez^{n_top}
+    const float *E_lev;       // forward Ez^{n_base + k} at E_lev + k * lev_stride
+    State in, out;            // lambda^{n_top} -> lambda^{n_top-nlev}
+    float *S1, *S2;           // per-shot correlation sums [S][NY][pitch]
+    const float *residual;    // [S][nt][R]
     float *src_adjoint;       // [S][nt] or null
+    const int *src_ij;
+    StreamGeom g;
 };
 
-// ---- launchers (fwi_kernels.hip) ------------------------------------------
+// ---- launchers ---------------------------------------------------------------
 
 hipError_t launch_coefficients(const float *eps_r, const float *sigma, float *Ca,
                                float *Cs, int NX, int NY, int pitch, double dt,
                                hipStream_t st);
 hipError_t launch_profiles(const Dims &d, const Profiles &p, hipStream_t st);
 hipError_t launch_fill(float *dst, size_t n, float v, hipStream_t st);
-hipError_t launch_fwd_step(const FwdStepArgs &a, hipStream_t st);
-hipError_t launch_adj_step(const AdjStepArgs &a, hipStream_t st);
-hipError_t launch_adj_inject(const float *residual, float *lE, const int *rec_ij,
-                             const int *order, const int *glen, int S, int R,
-                             int nt, int n, size_t plane, int pitch,
-                             hipStream_t st);
 hipError_t launch_gradient_finalize(const float *eps_r, const float *sigma,
-                                    const float *S1, const float *S2,
-                                    float *g_eps, float *g_sig, int NX, int NY,
-                                    int pitch, double dt, hipStream_t st);
+                                    const float *S1, const float *S2, int S,
+                                    size_t plane, float *g_eps, float *g_sig, int NX,
+                                    int NY, int pitch, double dt, hipStream_t st);
 hipError_t launch_residual_misfit(const float *traces, const float *observed,
                                   float *residual, size_t n, double *partials,
                                   double *misfit, hipStream_t st);
+// streaming kernels (fwi_stream.hip); the lean launchers return hipSuccess
+// without launching when the lean sub-grid is empty
+hipError_t launch_fwd_stream(const FwdStreamArgs &a, hipStream_t st);
+hipError_t launch_fwd_lean(const FwdStreamArgs &a, hipStream_t st);
+hipError_t launch_adj_stream(const AdjStreamArgs &a, hipStream_t st);
+hipError_t launch_adj_lean(const AdjStreamArgs &a, hipStream_t st);
 
 }  // namespace fwi

@@ -54,7 +54,8 @@ TIMING_MAX_KINDS = 8
 
 class fwi_kernel_time(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int32),
-                ("timed", ctypes.c_int32), ("avg_ms", ctypes.c_double)]
+                ("timed", ctypes.c_int32), ("avg_ms", ctypes.c_double),
+                ("cell_updates", ctypes.c_double)]
 
 
 class fwi_timing(ctypes.Structure):
@@ -64,7 +65,8 @@ class fwi_timing(ctypes.Structure):
     def as_dict(self):
         return {self.kind[k].name.decode(): dict(launches=self.kind[k].launches,
                                                  timed=self.kind[k].timed,
-                                                 avg_ms=self.kind[k].avg_ms)
+                                                 avg_ms=self.kind[k].avg_ms,
+                                                 cell_updates=self.kind[k].cell_updates)
                 for k in range(self.nkinds)}
 
 
