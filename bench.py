@@ -39,8 +39,7 @@ def log(*a):
 # Ez^n (28 B); Ca and Cs (8 B per cell) are shared by all shots.  One launch
 # advances several time levels; a gradient runs 2 nt forward levels (forward
 # sweep and checkpoint re-forward) and nt adjoint levels.
-PER_CELL_UPDATE = {"k_fwd_lean": 24.0, "k_fwd_stream": 24.0,
-                   "k_adj_lean": 28.0, "k_adj_stream": 28.0}
+PER_CELL_UPDATE = {"k_fwd": 24.0, "k_adj": 28.0}
 
 
 def algorithmic_bytes(kernel: str, cell_updates: float, shots: int) -> float:

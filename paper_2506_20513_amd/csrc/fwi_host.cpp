@@ -92,44 +92,30 @@ int choose_k(const Dims &d) {
     return std::max(1, std::min(K, d.nt));
 }
 
-// Streaming decomposition: x strips of 64 - 2K output columns and row bands.
-// The lean sub-grid is the set of strips and bands whose whole footprint
-// (K halo columns on each side, K rows above and below) avoids the CPML strips
-// and the outside of the grid: columns [npml, NX-2-npml], rows
-// [npml, NY-2-npml].  Bands: a top band [0, npml+K), interior bands, a bottom
-// band [NY-1-npml-K, NY); without a lean sub-grid, plain bands.
+// Streaming decomposition: x strips of 64 - 2K output columns, and row bands
+// chosen so that the waves fill whole rounds of the chip: each band costs 2K
+// rows of start-up on top of its own rows, and a last partial round of waves
+// leaves SIMDs idle; pick the band count with the least estimated time.
 void make_tiling(const Dims &d, Layout &L) {
     constexpr int K = kStreamK, OW = 64 - 2 * K;
-    const int target_waves = 4096;   // about four waves per SIMD
     const int max_bands = (int)(sizeof(L.bands) / sizeof(int)) - 1;
+    const double slots = 1024.0 * 4.0;   // 256 CUs x 4 SIMDs x ~4 resident waves
     L.nstrip = (d.NX + OW - 1) / OW;
-    // strip k is lean iff k*OW - K >= npml and k*OW - K + 63 <= NX - 2 - npml
-    int s0 = (d.npml + K + OW - 1) / OW;
-    const int hi = d.NX - 2 - d.npml - 63 + K;
-    int s1 = hi >= 0 ? hi / OW + 1 : 0;
-    const int yA = d.npml + K, yB = d.NY - 1 - d.npml - K;
-    int nb = 0;
-    auto split = [&](int lo, int hi_, int parts) {
-        const int h = (hi_ - lo + parts - 1) / parts;
-        for (int y = lo; y < hi_; y += h) L.bands[nb++] = y;
-    };
-    if (s1 > s0 && yB - yA >= 4 * K) {
-        const int nls = s1 - s0;
-        int parts = (target_waves + d.S * nls - 1) / (d.S * nls);
-        parts = std::max(1, std::min(parts, std::min((yB - yA) / (4 * K), max_bands - 2)));
-        L.bands[nb++] = 0;
-        split(yA, yB, parts);
-        L.lean_b0 = 1;
-        L.lean_b1 = nb;
-        L.bands[nb++] = yB;
-        L.lean_s0 = s0;
-        L.lean_s1 = s1;
-    } else {
-        int parts = (target_waves + d.S * L.nstrip - 1) / (d.S * L.nstrip);
-        parts = std::max(1, std::min(parts, std::min(d.NY / (4 * K) + 1, max_bands)));
-        split(0, d.NY, parts);
-        L.lean_s0 = L.lean_s1 = L.lean_b0 = L.lean_b1 = 0;
+    const double per_band = (double)d.S * L.nstrip;
+    int best = 1;
+    double best_t = 1e300;
+    for (int nb = 1; nb <= max_bands && nb <= (d.NY + 2 * K - 1) / (2 * K); ++nb) {
+        const int h = (d.NY + nb - 1) / nb;
+        const double rounds = std::ceil(per_band * nb / slots);
+        const double t = rounds * (h + 2.0 * K);
+        if (t < best_t * 0.999) {
+            best_t = t;
+            best = nb;
+        }
     }
+    const int h = (d.NY + best - 1) / best;
+    int nb = 0;
+    for (int y = 0; y < d.NY; y += h) L.bands[nb++] = y;
     L.nband = nb;
     L.bands[nb] = d.NY;
 }
@@ -250,15 +236,14 @@ struct Ptrs {
     } while (0)
 
 // Optional per-kernel timing with HIP events on the call's stream.
-enum Kind { K_FWD_LEAN = 0, K_FWD = 1, K_ADJ_LEAN = 2, K_ADJ = 3, K_NKINDS = 4 };
-const char *const kKindName[K_NKINDS] = {"k_fwd_lean", "k_fwd_stream", "k_adj_lean",
-                                         "k_adj_stream"};
+enum Kind { K_FWD = 0, K_ADJ = 1, K_NKINDS = 2 };
+const char *const kKindName[K_NKINDS] = {"k_fwd", "k_adj"};
 
 struct Timer {
     fwi_timing *t = nullptr;
     hipStream_t st = nullptr;
-    int launches[K_NKINDS] = {0, 0, 0, 0};
-    double updates[K_NKINDS] = {0, 0, 0, 0};
+    int launches[K_NKINDS] = {0, 0};
+    double updates[K_NKINDS] = {0, 0};
     struct Rec { int kind; hipEvent_t a, b; };
     std::vector<Rec> recs;
     bool failed = false;
@@ -285,8 +270,8 @@ struct Timer {
 
     int finish() {
         if (!t) return FWI_OK;
-        double sum[K_NKINDS] = {0, 0, 0, 0};
-        int cnt[K_NKINDS] = {0, 0, 0, 0};
+        double sum[K_NKINDS] = {0, 0};
+        int cnt[K_NKINDS] = {0, 0};
         int rc = FWI_OK;
         if (hipStreamSynchronize(st) != hipSuccess) rc = FWI_EHIP;
         for (auto &r : recs) {
@@ -387,18 +372,7 @@ Tiling tiling(const Ptrs &P) {
     t.bands = P.i(L.off_bands);
     t.nstrip = L.nstrip;
     t.nband = L.nband;
-    t.lean_s0 = L.lean_s0; t.lean_s1 = L.lean_s1;
-    t.lean_b0 = L.lean_b0; t.lean_b1 = L.lean_b1;
     return t;
-}
-
-// Cells owned by the lean sub-grid (all of its columns and rows are inside
-// the grid by construction).
-double lean_cells(const Layout &L) {
-    if (L.lean_s1 <= L.lean_s0) return 0.0;
-    const int OW = 64 - 2 * kStreamK;
-    return (double)(L.lean_s1 - L.lean_s0) * OW *
-           (double)(L.bands[L.lean_b1] - L.bands[L.lean_b0]);
 }
 
 StreamGeom stream_geom(const Ptrs &P, const fwi_geom *g) {
@@ -458,8 +432,6 @@ int forward_passes(const Ptrs &P, FwdStreamArgs a, int n0, int n1, int &cur, EIn
     State fs[2] = {P.state(L.off_fwd[0], false), P.state(L.off_fwd[1], false)};
     a.traces = traces;
     const double all = (double)L.d.NX * L.d.NY * L.d.S;
-    const double lean = lean_cells(L) * L.d.S;
-    const Tiling full = a.tl;
     for (int n = n0; n < n1; n += kStreamK) {
         a.n = n;
         a.nlev = std::min(kStreamK, n1 - n);
@@ -468,14 +440,7 @@ int forward_passes(const Ptrs &P, FwdStreamArgs a, int n0, int n1, int &cur, EIn
         a.E_out = a.E_lev ? nullptr : eout(n);
         a.in = fs[cur];
         a.out = fs[cur ^ 1];
-        // a pass shorter than K (end of the time axis) runs entirely in the
-        // general kernel
-        a.tl = full;
-        if (a.nlev < kStreamK) a.tl.lean_s0 = a.tl.lean_s1 = 0;
-        const double ln = a.tl.lean_s1 > a.tl.lean_s0 ? lean : 0.0;
-        if (ln > 0)
-            FWI_TRY(tm.run(K_FWD_LEAN, ln * a.nlev, [&] { return launch_fwd_lean(a, st); }));
-        FWI_TRY(tm.run(K_FWD, (all - ln) * a.nlev, [&] { return launch_fwd_stream(a, st); }));
+        FWI_TRY(tm.run(K_FWD, all * a.nlev, [&] { return launch_fwd_stream(a, st); }));
         cur ^= 1;
     }
     return FWI_OK;
@@ -562,8 +527,6 @@ int do_adjoint(const Layout &L, const fwi_geom *g, const float *eps_r,
     int acur = 0;
     // adjoint passes over steps [n_lo, n_hi), the forward Ez^{n_lo + k} in slot k
     const double all = (double)d.NX * d.NY * d.S;
-    const double lean = lean_cells(L) * d.S;
-    const Tiling full = a.tl;
     auto adj_range = [&](int n_hi, int n_lo) -> int {
         for (int n_top = n_hi; n_top > n_lo; n_top -= kStreamK) {
             a.nlev = std::min(kStreamK, n_top - n_lo);
@@ -573,12 +536,7 @@ int do_adjoint(const Layout &L, const fwi_geom *g, const float *eps_r,
             a.E_lev = P.slot(0);
             a.in = as[acur];
             a.out = as[acur ^ 1];
-            a.tl = full;
-            if (a.nlev < kStreamK) a.tl.lean_s0 = a.tl.lean_s1 = 0;
-            const double ln = a.tl.lean_s1 > a.tl.lean_s0 ? lean : 0.0;
-            if (ln > 0)
-                FWI_TRY(tm.run(K_ADJ_LEAN, ln * a.nlev, [&] { return launch_adj_lean(a, st); }));
-            FWI_TRY(tm.run(K_ADJ, (all - ln) * a.nlev, [&] { return launch_adj_stream(a, st); }));
+            FWI_TRY(tm.run(K_ADJ, all * a.nlev, [&] { return launch_adj_stream(a, st); }));
             acur ^= 1;
         }
         return FWI_OK;

@@ -61,7 +61,7 @@ struct Layout {
     int ncp;           // number of checkpoints
     int nslots;        // Ez slots
     // streaming decomposition (see Tiling)
-    int nstrip, nband, lean_s0, lean_s1, lean_b0, lean_b1;
+    int nstrip, nband;
     int bands[64];
     size_t off_Ca, off_Cs, off_prof;
     size_t off_src, off_rrow, off_rcol, off_ridx, off_rspan, off_bands;
@@ -78,7 +78,7 @@ struct Layout {
 // ---- kernel argument blocks -------------------------------------------------
 
 // Time levels advanced per pass of the streaming kernels.
-constexpr int kStreamK = 8;
+constexpr int kStreamK = 4;
 
 // Source and receiver tables on the device.  Receivers of each shot are
 // sorted by (row, column), stable in receiver index; rrow is the row CSR.
@@ -91,15 +91,11 @@ struct StreamGeom {
     const int *rspan;         // [S][2] first and last receiver row
 };
 
-// Row bands and the "lean" sub-grid.  bands[b] .. bands[b+1] are the rows a
-// wave of band b owns.  Waves with strip in [lean_s0, lean_s1) and band in
-// [lean_b0, lean_b1) touch no CPML cell and no cell outside the grid (their
-// whole footprint, halo included); they run the lean kernels and the general
-// kernels skip them.
+// Streaming decomposition: nstrip x-strips of 64 - 2K output columns and
+// nband row bands; bands[b] .. bands[b+1] are the rows a wave of band b owns.
 struct Tiling {
     const int *bands;         // [nband + 1]
     int nstrip, nband;
-    int lean_s0, lean_s1, lean_b0, lean_b1;
 };
 
 struct FwdStreamArgs {
@@ -150,11 +146,8 @@ hipError_t launch_gradient_finalize(const float *eps_r, const float *sigma,
 hipError_t launch_residual_misfit(const float *traces, const float *observed,
                                   float *residual, size_t n, double *partials,
                                   double *misfit, hipStream_t st);
-// streaming kernels (fwi_stream.hip); the lean launchers return hipSuccess
-// without launching when the lean sub-grid is empty
+// streaming kernels (fwi_stream.hip)
 hipError_t launch_fwd_stream(const FwdStreamArgs &a, hipStream_t st);
-hipError_t launch_fwd_lean(const FwdStreamArgs &a, hipStream_t st);
 hipError_t launch_adj_stream(const AdjStreamArgs &a, hipStream_t st);
-hipError_t launch_adj_lean(const AdjStreamArgs &a, hipStream_t st);
 
 }  // namespace fwi

@@ -5,19 +5,28 @@
 // Work decomposition.  One 64-lane wavefront owns one shot, one strip of 64
 // consecutive columns and one band of rows.  It marches down the rows of its
 // band; at every row it advances K time levels, level l working one row
-// behind level l-1 (the forward step needs the row below, the E update the
-// row above: the dependency cone widens by one row per level), so each field
+// behind level l-1 (the H step needs the row below, the E step the row
+// above, so the dependency cone widens by one row per level), so each field
 // row is read from HBM once per K time steps.  Lane = column; the x
 // neighbours of the stencil come from the neighbouring lanes through DPP
-// wavefront shifts, so no LDS and no barrier is involved.  The cone also
-// widens by one column per level, so after K levels the lanes
-// [K, 64-K) of the strip hold valid results: strips overlap by 2K columns and
-// only those lanes write.  Rows likewise: a band of rows [y0, y1) starts
-// streaming K rows above y0 and stops nlev rows below y1.
+// wavefront shifts, so no barrier is involved.  The cone also widens by one
+// column per level: after K levels the lanes [K, 64-K) of the strip hold
+// valid results, so strips overlap by 2K columns and only those lanes write.
+// Rows likewise: a band [y0, y1) starts streaming K rows above y0 and stops
+// nlev rows below y1.
+//
+// Registers.  A row carries five values from level to level (the three
+// fields and the two update coefficients).  Two register sets per level,
+// used alternately on even and odd rows, let each level write its output
+// straight into the input slot of the next level: the pipeline needs no
+// register copies.  The CPML memories are zero away from the CPML strips;
+// where they are not, they travel from level to level through a small LDS
+// ring (one row slot per level, per wave), level 0 taking them from
+// registers.
 //
 // Cells outside the grid hold zeros and the PEC ring has Ca = Cs = 0, so the
 // same arithmetic is correct everywhere without per-cell predicates (see the
-// notes at k_fwd_stream and k_adj_stream).
+// notes at k_fwd and k_adj).
 #include "fwi_internal.h"
 
 #include <type_traits>
@@ -34,12 +43,16 @@ __device__ __forceinline__ float from_right(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
 }
 
+// Column of the x-direction CPML strip store holding column i, or -1.
 __device__ __forceinline__ int xcol(int i, int NX, int npml) {
     if (i < npml) return i;
     if (i >= NX - 1 - npml) return i - (NX - 1 - npml) + npml;
     return -1;
 }
+// Row of the y-direction CPML strip store holding row j, or -1 (also for
+// rows outside the grid).
 __device__ __forceinline__ int yrow(int j, int NY, int npml) {
+    if (j < 0 || j >= NY) return -1;
     if (j < npml) return j;
     if (j >= NY - 1 - npml) return j - (NY - 1 - npml) + npml;
     return -1;
@@ -53,10 +66,6 @@ __device__ __forceinline__ int xcd_logical(int b, int nb) {
     const int per = nb / 8, rem = nb % 8;
     const int x = b % 8, k = b / 8;
     return x < rem ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
-}
-
-__device__ __forceinline__ bool is_lean(const Tiling &t, int strip, int band) {
-    return strip >= t.lean_s0 && strip < t.lean_s1 && band >= t.lean_b0 && band < t.lean_b1;
 }
 
 // Receivers of shot s on row j whose column lies in [c0, c1): index range
@@ -82,386 +91,88 @@ __device__ __forceinline__ void rec_range(const StreamGeom &g, int s, int NY, in
     hi = e;
 }
 
+// CPML constants of one row (y direction), scaled by 1/dy where the update
+// multiplies by it.  Outside the y strips kappa = 1 and a = 0.
+struct RowPml {
+    float chy, cyE, bHy, aHy, bEy, aEy;
+};
+__device__ __forceinline__ RowPml row_pml(const Profiles &p, int j, float ch, float rdy) {
+    RowPml r;
+    r.chy = ch * rdy * p.kHy[j];
+    r.cyE = rdy * p.kEy[j];
+    r.bHy = p.bHy[j];
+    r.aHy = p.aHy[j] * rdy;
+    r.bEy = p.bEy[j];
+    r.aEy = p.aEy[j] * rdy;
+    return r;
+}
+
+// Lane (column) constants: kappa, b and a of the x direction, scaled by 1/dx.
+struct ColPml {
+    float chx, cxE, bHx, aHx, bEx, aEx;
+};
+__device__ __forceinline__ ColPml col_pml(const Profiles &p, int i, bool inx, float ch,
+                                          float rdx) {
+    ColPml c{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (inx) {
+        c.chx = ch * rdx * p.kHx[i];
+        c.cxE = rdx * p.kEx[i];
+        c.bHx = p.bHx[i];
+        c.aHx = p.aHx[i] * rdx;
+        c.bEx = p.bEx[i];
+        c.aEx = p.aEx[i] * rdx;
+    }
+    return c;
+}
+
+struct WaveTile {
+    int s, x0, i, y0, y1;
+    bool inx, own;
+};
+template <int K>
+__device__ __forceinline__ WaveTile wave_tile(const Tiling &tl, int S, int NX) {
+    constexpr int OW = 64 - 2 * K;
+    WaveTile w;
+    const int wid = xcd_logical(blockIdx.x, gridDim.x);
+    w.s = wid % S;
+    const int strip = (wid / S) % tl.nstrip;
+    const int band = wid / (S * tl.nstrip);
+    w.x0 = strip * OW;
+    w.i = w.x0 - K + (int)threadIdx.x;
+    w.inx = w.i >= 0 && w.i < NX;
+    w.own = (int)threadIdx.x >= K && (int)threadIdx.x < K + OW && w.inx;
+    w.y0 = tl.bands[band];
+    w.y1 = tl.bands[band + 1];
+    return w;
+}
+
 // ---------------------------------------------------------------------------
-// Forward: K levels per pass.  Per level and row j (Algorithm 1, stages 1-6):
+// Forward: K levels per pass (TAIL: nlev < K levels).  Per level and row j
+// (Algorithm 1, stages 1-6):
 //   traces  <- Ez^{n+l}(j)                                 (owned cells only)
 //   Hx(j)   -= ch/dy * (Ez(j+1)-Ez(j))/kappa_Hy + ch psi_hx'
 //   Hy(i)   += ch/dx * (Ez(i+1)-Ez(i))/kappa_Hx + ch psi_hy'
 //   Ez      <- Ca Ez + Cs [ dHy/dx/kappa_Ex + psi_ex' - dHx/dy/kappa_Ey - psi_ey' ]
 //   Ez(src) -= Cs w[n+l] / (dx dy)                         (every lane holding it)
 // With zeros outside the grid, Ez = 0 and Ca = Cs = 0 on the PEC ring, the
-// H rows/columns that the oracle does not update (Hx at j = NY-1, Hy at
+// H rows/columns that the E update never reads (Hx at j = NY-1, Hy at
 // i = NX-1) see a zero difference and stay zero, and ring Ez stays zero.
-struct FRow {
-    float E, Hx, Hy, Ca, Cs, phx, phy, pex, pey;
-};
-
-template <int K>
-__global__ __launch_bounds__(64) void k_fwd_stream(FwdStreamArgs a) {
+// psi is a float4 (psi_hx, psi_hy, psi_ex, psi_ey).
+template <int K, bool TAIL>
+__global__ __launch_bounds__(64) void k_fwd(FwdStreamArgs a) {
+    static_assert((K & (K - 1)) == 0, "K must be a power of two");
     constexpr int OW = 64 - 2 * K;
+    __shared__ float4 ring[K][64];
     const int lane = threadIdx.x;
-    const int wid = xcd_logical(blockIdx.x, gridDim.x);
-    const int s = wid % a.S;
-    const int strip = (wid / a.S) % a.tl.nstrip;
-    const int band = wid / (a.S * a.tl.nstrip);
-    if (is_lean(a.tl, strip, band)) return;
-    const int NX = a.NX, NY = a.NY, P = a.pitch;
-    const int x0 = strip * OW;
-    const int i = x0 - K + lane;
-    const bool inx = i >= 0 && i < NX;
-    const bool own = lane >= K && lane < K + OW && inx;
-    const int y0 = a.tl.bands[band];
-    const int y1 = a.tl.bands[band + 1];
-    const int nlev = a.nlev;
-    const int cx = inx ? xcol(i, NX, a.npml) : -1;
-
+    const WaveTile w = wave_tile<K>(a.tl, a.S, a.NX);
+    const int s = w.s, i = w.i, y0 = w.y0, y1 = w.y1;
+    const int NY = a.NY, P = a.pitch, npml = a.npml;
+    const int nlev = TAIL ? a.nlev : K;
+    const int cx = w.inx ? xcol(i, a.NX, npml) : -1;
+    const bool xp = cx >= 0;
     const float ch = a.ch, rdx = a.rdx, rdy = a.rdy;
-    float chx = 0.f, cxE = 0.f, bHx = 0.f, aHx = 0.f, bEx = 0.f, aEx = 0.f;
-    if (inx) {
-        chx = ch * rdx * a.p.kHx[i];
-        cxE = rdx * a.p.kEx[i];
-        bHx = a.p.bHx[i];
-        aHx = a.p.aHx[i] * rdx;
-        bEx = a.p.bEx[i];
-        aEx = a.p.aEx[i] * rdx;
-    }
-    const int si = a.g.src_ij[2 * s], sj = a.g.src_ij[2 * s + 1];
-    const size_t so = (size_t)s * a.plane;
-    const float *__restrict__ Ein = a.E_in + so;
-    const float *__restrict__ Hxin = a.in.Hx + so;
-    const float *__restrict__ Hyin = a.in.Hy + so;
-    const float *__restrict__ wav = a.g.wavelet + (size_t)s * a.nt + a.n;
-    const int rlast = min(NY - 1, y1 + nlev - 1);   // last input row needed
-
-    auto load = [&](int r) {
-        FRow v{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if (r >= 0 && r <= rlast && inx) {
-            const size_t k = (size_t)r * P + i;
-            v.E = Ein[k];
-            v.Hx = Hxin[k];
-            v.Hy = Hyin[k];
-            v.Ca = a.Ca[k];
-            v.Cs = a.Cs[k];
-            const int ry = yrow(r, NY, a.npml);
-            if (ry >= 0) {
-                const size_t q = (size_t)s * a.ys + (size_t)ry * P + i;
-                v.phx = a.in.phx[q];
-                v.pey = a.in.pey[q];
-            }
-            if (cx >= 0) {
-                const size_t q = (size_t)s * a.xs + (size_t)r * a.W + cx;
-                v.phy = a.in.phy[q];
-                v.pex = a.in.pex[q];
-            }
-        }
-        return v;
-    };
-
-    FRow prev[K];
-    float hprev[K];
-#pragma unroll
-    for (int l = 0; l < K; ++l) {
-        prev[l] = FRow{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        hprev[l] = 0.f;
-    }
-
-    const int T = (y1 - y0) + K + nlev;
-    FRow nxt = load(y0 - K);
-    for (int t = 0; t < T; ++t) {
-        const int r = y0 - K + t;
-        FRow in = nxt;
-        nxt = load(r + 1);
-#pragma unroll
-        for (int l = 0; l < K; ++l) {
-            if (l < nlev) {
-                const int j = r - 1 - l;            // row this level updates
-                const FRow &p = prev[l];
-                FRow o{0.f, 0.f, 0.f, p.Ca, p.Cs, 0.f, 0.f, 0.f, 0.f};
-                const bool jin = j >= 0 && j < NY;
-                const bool jown = jin && j >= y0 && j < y1;
-                if (a.traces && jown) {             // stage 1: Ez^{n+l} at receivers
-                    int lo, hi;
-                    rec_range(a.g, s, NY, a.R, j, x0, x0 + OW, lo, hi);
-                    for (int q = lo; q < hi; ++q) {
-                        if (own && a.g.rcol[(size_t)s * a.R + q] == i)
-                            a.traces[((size_t)s * a.nt + a.n + l) * a.R +
-                                     a.g.ridx[(size_t)s * a.R + q]] = p.E;
-                    }
-                }
-                if (jin) {
-                    const float kHy = a.p.kHy[j], kEy = a.p.kEy[j];
-                    const int ry = yrow(j, NY, a.npml);
-                    // stages 2-3: H to n+l+1/2
-                    const float dEy = in.E - p.E;
-                    float hx = p.Hx - (ch * rdy * kHy) * dEy;
-                    if (ry >= 0) {
-                        o.phx = a.p.bHy[j] * p.phx + (a.p.aHy[j] * rdy) * dEy;
-                        hx -= ch * o.phx;
-                    }
-                    const float dEx = from_right(p.E) - p.E;
-                    float hy = p.Hy + chx * dEx;
-                    if (cx >= 0) {
-                        o.phy = bHx * p.phy + aHx * dEx;
-                        hy += ch * o.phy;
-                    }
-                    // stages 4-6: E to n+l+1
-                    const float dHy = hy - from_left(hy);
-                    const float dHx = hx - hprev[l];
-                    float curl = dHy * cxE - dHx * (rdy * kEy);
-                    if (cx >= 0) {
-                        o.pex = bEx * p.pex + aEx * dHy;
-                        curl += o.pex;
-                    }
-                    if (ry >= 0) {
-                        o.pey = a.p.bEy[j] * p.pey + (a.p.aEy[j] * rdy) * dHx;
-                        curl -= o.pey;
-                    }
-                    float e = p.Ca * p.E + p.Cs * curl;
-                    if (j == sj && i == si) e -= p.Cs * wav[l] * a.src_scale;
-                    o.E = e;
-                    o.Hx = hx;
-                    o.Hy = hy;
-                }
-                hprev[l] = o.Hx;
-                if (jown && own) {
-                    const size_t k = (size_t)j * P + i;
-                    if (a.E_lev) a.E_lev[(size_t)l * a.lev_stride + so + k] = o.E;
-                    if (l == nlev - 1) {
-                        if (!a.E_lev) a.E_out[so + k] = o.E;
-                        a.out.Hx[so + k] = o.Hx;
-                        a.out.Hy[so + k] = o.Hy;
-                        const int ry = yrow(j, NY, a.npml);
-                        if (ry >= 0) {
-                            const size_t q = (size_t)s * a.ys + (size_t)ry * P + i;
-                            a.out.phx[q] = o.phx;
-                            a.out.pey[q] = o.pey;
-                        }
-                        if (cx >= 0) {
-                            const size_t q = (size_t)s * a.xs + (size_t)j * a.W + cx;
-                            a.out.phy[q] = o.phy;
-                            a.out.pex[q] = o.pex;
-                        }
-                    }
-                }
-                prev[l] = in;
-                in = o;
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Adjoint: K levels per pass, level l taking lambda^{n+1} to lambda^n for
-// n = n_top-1-l (the exact transpose of the forward step, followed by the
-// adjoint source).  Per row j of a level:
-//   on arrival of row j (A1, cell-local):  g = Cs lE,
-//       LDx = g/(kx dx) + ax/dx (phi_ex + g),  phi_ex <- bx (phi_ex + g)
-//       LDy = -g/(ky dy) + ay/dy (phi_ey - g), phi_ey <- by (phi_ey - g)
-//   imaging (A0, owned cells): S1 += lE (E^{n+1} - E^n), S2 += lE (E^{n+1} + E^n)
-//   lHy += LDx(i) - LDx(i+1);  lHx += LDy(j) - LDy(j+1)               (A1)
-//   h = ch lHy: LDex = (h/kx + ax (phi_hy + h))/dx, phi_hy <- bx (phi_hy + h)
-//   h = ch lHx: LDey = (-h/ky + ay (phi_hx - h))/dy, phi_hx <- by (phi_hx - h)
-//   lE <- Ca lE + LDex(i-1) - LDex(i) + LDey(j-1) - LDey(j)           (A2)
-//   lE(rec) += residual[n]          (A3, every lane holding the receiver)
-// With Ca = Cs = 0 on the ring and zeros outside the grid, g, LDx and LDy
-// vanish there, so the adjoint H values the oracle never touches stay zero;
-// lE on the ring picks up terms but never feeds back (its g is zero), which
-// matches the oracle where the ring is not a state variable.
-struct ARow {
-    float lE, Ca, Cs, ldx, ldy, pex, pey, lHx, lHy, phx, phy, Enp1, s1, s2;
-};
-
-template <int K>
-__global__ __launch_bounds__(64) void k_adj_stream(AdjStreamArgs a) {
-    constexpr int OW = 64 - 2 * K;
-    const int lane = threadIdx.x;
-    const int wid = xcd_logical(blockIdx.x, gridDim.x);
-    const int s = wid % a.S;
-    const int strip = (wid / a.S) % a.tl.nstrip;
-    const int band = wid / (a.S * a.tl.nstrip);
-    if (is_lean(a.tl, strip, band)) return;
-    const int NX = a.NX, NY = a.NY, P = a.pitch;
-    const int x0 = strip * OW;
-    const int i = x0 - K + lane;
-    const bool inx = i >= 0 && i < NX;
-    const bool own = lane >= K && lane < K + OW && inx;
-    const int y0 = a.tl.bands[band];
-    const int y1 = a.tl.bands[band + 1];
-    const int nlev = a.nlev;
-    const int cx = inx ? xcol(i, NX, a.npml) : -1;
-
-    const float ch = a.ch, rdx = a.rdx, rdy = a.rdy;
-    float chx = 0.f, cxE = 0.f, bHx = 0.f, aHx = 0.f, bEx = 0.f, aEx = 0.f;
-    if (inx) {
-        chx = ch * rdx * a.p.kHx[i];
-        cxE = rdx * a.p.kEx[i];
-        bHx = a.p.bHx[i];
-        aHx = a.p.aHx[i] * rdx;
-        bEx = a.p.bEx[i];
-        aEx = a.p.aEx[i] * rdx;
-    }
-    const int si = a.src_ij[2 * s], sj = a.src_ij[2 * s + 1];
-    const size_t so = (size_t)s * a.plane;
-    const float *__restrict__ Lin = a.in.E + so;
-    const float *__restrict__ LHxin = a.in.Hx + so;
-    const float *__restrict__ LHyin = a.in.Hy + so;
-    const int rlast = min(NY - 1, y1 + nlev - 1);
-
-    // A1 for a row on arrival: cell-local terms
-    auto arrive = [&](ARow &v, int r) {
-        if (r < 0 || r >= NY) return;
-        const float g = v.Cs * v.lE;
-        const float tx = v.pex + g;
-        const float ty = v.pey - g;
-        v.ldx = g * cxE + aEx * tx;
-        v.ldy = -g * (rdy * a.p.kEy[r]) + (a.p.aEy[r] * rdy) * ty;
-        if (cx >= 0) v.pex = bEx * tx;
-        if (yrow(r, NY, a.npml) >= 0) v.pey = a.p.bEy[r] * ty;
-    };
-    auto load = [&](int r) {
-        ARow v{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if (r >= 0 && r <= rlast && inx) {
-            const size_t k = (size_t)r * P + i;
-            v.lE = Lin[k];
-            v.lHx = LHxin[k];
-            v.lHy = LHyin[k];
-            v.Ca = a.Ca[k];
-            v.Cs = a.Cs[k];
-            v.Enp1 = a.E_top[so + k];
-            const int ry = yrow(r, NY, a.npml);
-            if (ry >= 0) {
-                const size_t q = (size_t)s * a.ys + (size_t)ry * P + i;
-                v.phx = a.in.phx[q];
-                v.pey = a.in.pey[q];
-            }
-            if (cx >= 0) {
-                const size_t q = (size_t)s * a.xs + (size_t)r * a.W + cx;
-                v.phy = a.in.phy[q];
-                v.pex = a.in.pex[q];
-            }
-        }
-        return v;
-    };
-
-    ARow prev[K];
-    float ldey_prev[K];
-#pragma unroll
-    for (int l = 0; l < K; ++l) {
-        prev[l] = ARow{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        ldey_prev[l] = 0.f;
-    }
-
-    const int T = (y1 - y0) + K + nlev;
-    ARow nxt = load(y0 - K);
-    for (int t = 0; t < T; ++t) {
-        const int r = y0 - K + t;
-        ARow in = nxt;
-        arrive(in, r);
-        nxt = load(r + 1);
-#pragma unroll
-        for (int l = 0; l < K; ++l) {
-            if (l < nlev) {
-                const int j = r - 1 - l;
-                const int n = a.n_top - 1 - l;
-                const ARow &p = prev[l];
-                const bool jin = j >= 0 && j < NY;
-                const bool jown = jin && j >= y0 && j < y1;
-                ARow o{0.f, p.Ca, p.Cs, 0.f, 0.f, p.pex, p.pey, 0.f, 0.f, 0.f, 0.f, 0.f,
-                       p.s1, p.s2};
-                float ldey = 0.f;
-                if (jin) {
-                    // forward Ez^n of this row (Ez^{n+1} came with the row)
-                    const float en = inx ? a.E_lev[(size_t)(n - a.n_base) * a.lev_stride + so +
-                                                   (size_t)j * P + i]
-                                         : 0.f;
-                    o.Enp1 = en;
-                    // A0 imaging with lambda_E^{n+1}
-                    if (own && jown) {
-                        o.s1 += p.lE * (p.Enp1 - en);
-                        o.s2 += p.lE * (p.Enp1 + en);
-                    }
-                    if (a.src_adjoint && own && j == sj && i == si)
-                        a.src_adjoint[(size_t)s * a.nt + n] = -p.Cs * p.lE * a.src_scale;
-                    // A1: lambda_H after the transposed E step
-                    const float lhy = p.lHy + (p.ldx - from_right(p.ldx));
-                    const float lhx = p.lHx + (p.ldy - in.ldy);
-                    // A2: transposed H step
-                    const float kHy = a.p.kHy[j];
-                    const int ry = yrow(j, NY, a.npml);
-                    float ldex = lhy * chx;
-                    if (cx >= 0) {
-                        const float t1 = p.phy + ch * lhy;
-                        ldex += aHx * t1;
-                        o.phy = bHx * t1;
-                    }
-                    ldey = -lhx * (ch * rdy * kHy);
-                    if (ry >= 0) {
-                        const float t2 = p.phx - ch * lhx;
-                        ldey += (a.p.aHy[j] * rdy) * t2;
-                        o.phx = a.p.bHy[j] * t2;
-                    }
-                    float le = p.Ca * p.lE + (from_left(ldex) - ldex) + (ldey_prev[l] - ldey);
-                    // A3: adjoint source of step n
-                    int lo, hi;
-                    rec_range(a.g, s, NY, a.R, j, x0 - K, x0 - K + 64, lo, hi);
-                    const float *res = a.residual + ((size_t)s * a.nt + n) * a.R;
-                    for (int q = lo; q < hi; ++q)
-                        if (a.g.rcol[(size_t)s * a.R + q] == i)
-                            le += res[a.g.ridx[(size_t)s * a.R + q]];
-                    o.lE = le;
-                    o.lHx = lhx;
-                    o.lHy = lhy;
-                }
-                ldey_prev[l] = ldey;
-                if (jown && own && l == nlev - 1) {
-                    const size_t k = (size_t)j * P + i;
-                    a.out.E[so + k] = o.lE;
-                    a.out.Hx[so + k] = o.lHx;
-                    a.out.Hy[so + k] = o.lHy;
-                    a.S1[so + k] += o.s1;
-                    a.S2[so + k] += o.s2;
-                    const int ry = yrow(j, NY, a.npml);
-                    if (ry >= 0) {
-                        const size_t q = (size_t)s * a.ys + (size_t)ry * P + i;
-                        a.out.phx[q] = o.phx;
-                        a.out.pey[q] = o.pey;
-                    }
-                    if (cx >= 0) {
-                        const size_t q = (size_t)s * a.xs + (size_t)j * a.W + cx;
-                        a.out.phy[q] = o.phy;
-                        a.out.pex[q] = o.pex;
-                    }
-                }
-                prev[l] = in;
-                in = o;
-                arrive(in, j);
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Lean kernels: waves of the lean sub-grid (see Tiling), full passes of K
-// levels.  No CPML memory (zero away from the strips), kappa = 1, every lane
-// inside the grid, so each level is the bare stencil.  A row carries five
-// values from level to level; two register sets per level, used alternately
-// on even and odd rows, let every level write its output straight into the
-// input slot of the next level, so the pipeline needs no register copies.
-template <int K>
-__global__ __launch_bounds__(64) void k_fwd_lean(FwdStreamArgs a) {
-    constexpr int OW = 64 - 2 * K;
-    const int lane = threadIdx.x;
-    const int nsl = a.tl.lean_s1 - a.tl.lean_s0;
-    const int wid = xcd_logical(blockIdx.x, gridDim.x);
-    const int s = wid % a.S;
-    const int strip = a.tl.lean_s0 + (wid / a.S) % nsl;
-    const int band = a.tl.lean_b0 + wid / (a.S * nsl);
-    const int P = a.pitch;
-    const int x0 = strip * OW;
-    const int i = x0 - K + lane;
-    const bool own = lane >= K && lane < K + OW;
-    const int y0 = a.tl.bands[band], y1 = a.tl.bands[band + 1];
-    const float chx = a.ch * a.rdx, chy = a.ch * a.rdy, cxE = a.rdx, cyE = a.rdy;
+    const ColPml c = col_pml(a.p, i, w.inx, ch, rdx);
+    const RowPml r0{ch * rdy, rdy, 0.f, 0.f, 0.f, 0.f};
     const int si = a.g.src_ij[2 * s], sj = a.g.src_ij[2 * s + 1];
     const int rlo = a.g.rspan[2 * s], rhi = a.g.rspan[2 * s + 1];
     const size_t so = (size_t)s * a.plane;
@@ -469,9 +180,10 @@ __global__ __launch_bounds__(64) void k_fwd_lean(FwdStreamArgs a) {
     const float *__restrict__ Hxin = a.in.Hx + so;
     const float *__restrict__ Hyin = a.in.Hy + so;
     const float *__restrict__ wav = a.g.wavelet + (size_t)s * a.nt + a.n;
-    float *__restrict__ Hxo = a.out.Hx + so;
-    float *__restrict__ Hyo = a.out.Hy + so;
-    const int rlast = y1 + K - 1;
+    const int rlast = min(NY - 1, y1 + nlev - 1);
+
+#pragma unroll
+    for (int l = 0; l < K; ++l) ring[l][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
 
     float E_[2][K], Hx_[2][K], Hy_[2][K], Ca_[2][K], Cs_[2][K];
 #pragma unroll
@@ -479,18 +191,31 @@ __global__ __launch_bounds__(64) void k_fwd_lean(FwdStreamArgs a) {
         E_[0][l] = E_[1][l] = Hx_[0][l] = Hx_[1][l] = Hy_[0][l] = Hy_[1][l] = 0.f;
         Ca_[0][l] = Ca_[1][l] = Cs_[0][l] = Cs_[1][l] = 0.f;
     }
+    float4 ps0[2] = {make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f)};
     float hlast = 0.f;
     float nE = 0.f, nHx = 0.f, nHy = 0.f, nCa = 0.f, nCs = 0.f;
+    float4 nPs = make_float4(0.f, 0.f, 0.f, 0.f);
     auto load = [&](int r) {
-        if (r <= rlast) {
+        nE = nHx = nHy = nCa = nCs = 0.f;
+        nPs = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (r >= 0 && r <= rlast && w.inx) {
             const size_t k = (size_t)r * P + i;
             nE = Ein[k];
             nHx = Hxin[k];
             nHy = Hyin[k];
             nCa = a.Ca[k];
             nCs = a.Cs[k];
-        } else {
-            nE = nHx = nHy = nCa = nCs = 0.f;
+            const int ry = yrow(r, NY, npml);
+            if (ry >= 0) {
+                const size_t q = (size_t)s * a.ys + (size_t)ry * P + i;
+                nPs.x = a.in.phx[q];
+                nPs.w = a.in.pey[q];
+            }
+            if (xp) {
+                const size_t q = (size_t)s * a.xs + (size_t)r * a.W + cx;
+                nPs.y = a.in.phy[q];
+                nPs.z = a.in.pex[q];
+            }
         }
     };
     load(y0 - K);
@@ -499,108 +224,180 @@ __global__ __launch_bounds__(64) void k_fwd_lean(FwdStreamArgs a) {
         constexpr int p = decltype(pc)::value, q = 1 - p;
         const int r = y0 - K + t;
         E_[q][0] = nE; Hx_[q][0] = nHx; Hy_[q][0] = nHy; Ca_[q][0] = nCa; Cs_[q][0] = nCs;
+        ps0[q] = nPs;
         load(r + 1);
 #pragma unroll
         for (int l = 0; l < K; ++l) {
+            if (TAIL && l >= nlev) continue;
+            const bool last = TAIL ? l == nlev - 1 : l == K - 1;
             const int j = r - 1 - l;
             const float pE = E_[p][l], pCa = Ca_[p][l], pCs = Cs_[p][l];
             const float hprev = (l + 1 < K) ? Hx_[p][l + 1] : hlast;
             const bool jown = j >= y0 && j < y1;
-            if (a.traces && jown && j >= rlo && j <= rhi) {
+            if (a.traces && jown && j >= rlo && j <= rhi) {    // stage 1
                 int lo, hi;
-                rec_range(a.g, s, a.NY, a.R, j, x0, x0 + OW, lo, hi);
+                rec_range(a.g, s, NY, a.R, j, w.x0, w.x0 + OW, lo, hi);
                 for (int q2 = lo; q2 < hi; ++q2)
-                    if (own && a.g.rcol[(size_t)s * a.R + q2] == i)
+                    if (w.own && a.g.rcol[(size_t)s * a.R + q2] == i)
                         a.traces[((size_t)s * a.nt + a.n + l) * a.R +
                                  a.g.ridx[(size_t)s * a.R + q2]] = pE;
             }
-            const float hx = Hx_[p][l] - chy * (E_[q][l] - pE);
-            const float hy = Hy_[p][l] + chx * (from_right(pE) - pE);
-            float e = pCa * pE + pCs * ((hy - from_left(hy)) * cxE - (hx - hprev) * cyE);
+            const int ry = yrow(j, NY, npml);
+            const bool yp = ry >= 0;
+            const RowPml rp = yp ? row_pml(a.p, j, ch, rdy) : r0;
+            // stages 2-3: H to n+l+1/2
+            const float dEy = E_[q][l] - pE;
+            const float dEx = from_right(pE) - pE;
+            float hx = Hx_[p][l] - rp.chy * dEy;
+            float hy = Hy_[p][l] + c.chx * dEx;
+            float4 ps = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (yp || xp) ps = l == 0 ? ps0[p] : ring[j & (K - 1)][lane];
+            if (yp) {
+                ps.x = rp.bHy * ps.x + rp.aHy * dEy;
+                hx -= ch * ps.x;
+            }
+            if (xp) {
+                ps.y = c.bHx * ps.y + c.aHx * dEx;
+                hy += ch * ps.y;
+            }
+            // stages 4-6: E to n+l+1
+            const float dHy = hy - from_left(hy);
+            const float dHx = hx - hprev;
+            float curl = dHy * c.cxE - dHx * rp.cyE;
+            if (xp) {
+                ps.z = c.bEx * ps.z + c.aEx * dHy;
+                curl += ps.z;
+            }
+            if (yp) {
+                ps.w = rp.bEy * ps.w + rp.aEy * dHx;
+                curl -= ps.w;
+            }
+            float e = pCa * pE + pCs * curl;
             if (j == sj && i == si) e -= pCs * wav[l] * a.src_scale;
             if (l + 1 < K) {
                 E_[q][l + 1] = e; Hx_[q][l + 1] = hx; Hy_[q][l + 1] = hy;
                 Ca_[q][l + 1] = pCa; Cs_[q][l + 1] = pCs;
+                if ((yp || xp) && !last) ring[j & (K - 1)][lane] = ps;
             } else {
                 hlast = hx;
             }
-            if (jown && own) {
+            if (jown && w.own) {
                 const size_t k = (size_t)j * P + i;
                 if (a.E_lev) a.E_lev[(size_t)l * a.lev_stride + so + k] = e;
-                if (l == K - 1) {
+                if (last) {
                     if (!a.E_lev) a.E_out[so + k] = e;
-                    Hxo[k] = hx;
-                    Hyo[k] = hy;
+                    a.out.Hx[so + k] = hx;
+                    a.out.Hy[so + k] = hy;
+                    if (yp) {
+                        const size_t q2 = (size_t)s * a.ys + (size_t)ry * P + i;
+                        a.out.phx[q2] = ps.x;
+                        a.out.pey[q2] = ps.w;
+                    }
+                    if (xp) {
+                        const size_t q2 = (size_t)s * a.xs + (size_t)j * a.W + cx;
+                        a.out.phy[q2] = ps.y;
+                        a.out.pex[q2] = ps.z;
+                    }
                 }
             }
         }
     };
-    const int T = (y1 - y0) + 2 * K;
+    const int T = (y1 - y0) + K + nlev;
     for (int t = 0; t < T; t += 2) {
         iter(std::integral_constant<int, 0>(), t);
         iter(std::integral_constant<int, 1>(), t + 1);
     }
 }
 
-// Lean adjoint.  The imaging sums use a regrouped form of Eqs. (12)-(13):
-// because lambda^{nt} = 0 and Ez^0 = 0,
+// ---------------------------------------------------------------------------
+// Adjoint: K levels per pass, level l taking lambda^{n+1} to lambda^n for
+// n = n_top-1-l: the exact transpose of the forward step, then the adjoint
+// source.  Per row j of a level (row j+1 is the one below):
+//   A1  g = Cs lE; LDx = g/(kx dx) + ax/dx (phi_ex + g),  phi_ex <- bx (phi_ex + g)
+//                  LDy = -g/(ky dy) + ay/dy (phi_ey - g), phi_ey <- by (phi_ey - g)
+//       lHy += LDx(i) - LDx(i+1);  lHx += LDy(j) - LDy(j+1)
+//   A2  h = ch lHy: LDex = (h/kx + ax (phi_hy + h))/dx, phi_hy <- bx (phi_hy + h)
+//       h = ch lHx: LDey = (-h/ky + ay (phi_hx - h))/dy, phi_hx <- by (phi_hx - h)
+//       lE <- Ca lE + LDex(i-1) - LDex(i) + LDey(j-1) - LDey(j)
+//   A3  lE(rec) += residual[n]                     (every lane holding it)
+// With Ca = Cs = 0 on the ring and zeros outside the grid, g and hence the
+// adjoint H values the forward never reads stay zero; lE on the ring picks
+// up terms but never feeds back (its g is zero), matching the oracle where
+// the ring is not a state variable.  phi is a float4 (phi_ex, phi_ey,
+// phi_hx, phi_hy).
+//
+// Imaging uses a regrouped form of Eqs. (12)-(13): because lambda^{nt} = 0
+// and Ez^0 = 0,
 //   S1 = sum_n lambda^{n+1} (E^{n+1} - E^n) = sum_n E^n (lambda^n - lambda^{n+1})
 //   S2 = sum_n lambda^{n+1} (E^{n+1} + E^n) = sum_n E^n (lambda^n + lambda^{n+1})
-// with lambda^n the state after the adjoint source of step n.  A level then
-// needs only the forward Ez^n of its own step; the partial sums of the rows in
-// flight live in a small LDS ring, one row per level.
-template <int K>
-__global__ __launch_bounds__(64) void k_adj_lean(AdjStreamArgs a) {
+// with lambda^n the state after the adjoint source of step n, so a level
+// needs only the forward Ez^n of its own step (prefetched a row ahead); the
+// partial sums of the rows in flight live in a second LDS ring.
+template <int K, bool TAIL>
+__global__ __launch_bounds__(64) void k_adj(AdjStreamArgs a) {
     static_assert((K & (K - 1)) == 0, "K must be a power of two");
-    constexpr int OW = 64 - 2 * K;
-    __shared__ float2 ring[K][64];
+    __shared__ float4 ring[K][64];
+    __shared__ float2 img[K][64];
     const int lane = threadIdx.x;
-    const int nsl = a.tl.lean_s1 - a.tl.lean_s0;
-    const int wid = xcd_logical(blockIdx.x, gridDim.x);
-    const int s = wid % a.S;
-    const int strip = a.tl.lean_s0 + (wid / a.S) % nsl;
-    const int band = a.tl.lean_b0 + wid / (a.S * nsl);
-    const int P = a.pitch, NY = a.NY;
-    const int x0 = strip * OW;
-    const int i = x0 - K + lane;
-    const bool own = lane >= K && lane < K + OW;
-    const int y0 = a.tl.bands[band], y1 = a.tl.bands[band + 1];
-    const float chx = a.ch * a.rdx, chy = a.ch * a.rdy, cxE = a.rdx, cyE = a.rdy;
+    const WaveTile w = wave_tile<K>(a.tl, a.S, a.NX);
+    const int s = w.s, i = w.i, y0 = w.y0, y1 = w.y1;
+    const int NY = a.NY, P = a.pitch, npml = a.npml;
+    const int nlev = TAIL ? a.nlev : K;
+    const int cx = w.inx ? xcol(i, a.NX, npml) : -1;
+    const bool xp = cx >= 0;
+    const float ch = a.ch, rdx = a.rdx, rdy = a.rdy;
+    const ColPml c = col_pml(a.p, i, w.inx, ch, rdx);
+    const RowPml r0{ch * rdy, rdy, 0.f, 0.f, 0.f, 0.f};
     const int si = a.src_ij[2 * s], sj = a.src_ij[2 * s + 1];
     const int rlo = a.g.rspan[2 * s], rhi = a.g.rspan[2 * s + 1];
     const size_t so = (size_t)s * a.plane;
     const float *__restrict__ Lin = a.in.E + so;
     const float *__restrict__ LHxin = a.in.Hx + so;
     const float *__restrict__ LHyin = a.in.Hy + so;
-    const float *__restrict__ Ef = a.E_lev + so + i;
-    const int rlast = y1 + K - 1;
+    const float *__restrict__ Ef = a.E_lev + so + (w.inx ? i : 0);
+    const int rlast = min(NY - 1, y1 + nlev - 1);
 
-    float L_[2][K], Ca_[2][K], Cs_[2][K], Hx_[2][K], Hy_[2][K];
-    float ldey_prev[K], en_pf[K];
-    // forward Ez^{n_l}(j) for level l (n_l = n_top - 1 - l), 0 off the grid
+    // forward Ez^{n_l}(j) of level l (n_l = n_top - 1 - l), 0 off the grid
     auto loadE = [&](int l, int j) {
-        return (j >= 0 && j < NY)
+        return (j >= 0 && j < NY && w.inx)
                    ? Ef[(size_t)(a.n_top - 1 - l - a.n_base) * a.lev_stride + (size_t)j * P]
                    : 0.f;
     };
+
+    float L_[2][K], Ca_[2][K], Cs_[2][K], Hx_[2][K], Hy_[2][K];
+    float ldey_prev[K], en_pf[K];
 #pragma unroll
     for (int l = 0; l < K; ++l) {
+        ring[l][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
         L_[0][l] = L_[1][l] = Ca_[0][l] = Ca_[1][l] = Cs_[0][l] = Cs_[1][l] = 0.f;
         Hx_[0][l] = Hx_[1][l] = Hy_[0][l] = Hy_[1][l] = 0.f;
         ldey_prev[l] = 0.f;
-        en_pf[l] = loadE(l, y0 - K - 1 - l);
+        en_pf[l] = (TAIL && l >= nlev) ? 0.f : loadE(l, y0 - K - 1 - l);
     }
+    float4 ph0[2] = {make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f)};
     float nL = 0.f, nCa = 0.f, nCs = 0.f, nHx = 0.f, nHy = 0.f;
+    float4 nPh = make_float4(0.f, 0.f, 0.f, 0.f);
     auto load = [&](int r) {
-        if (r <= rlast) {
+        nL = nCa = nCs = nHx = nHy = 0.f;
+        nPh = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (r >= 0 && r <= rlast && w.inx) {
             const size_t k = (size_t)r * P + i;
             nL = Lin[k];
             nHx = LHxin[k];
             nHy = LHyin[k];
             nCa = a.Ca[k];
             nCs = a.Cs[k];
-        } else {
-            nL = nHx = nHy = nCa = nCs = 0.f;
+            const int ry = yrow(r, NY, npml);
+            if (ry >= 0) {
+                const size_t q = (size_t)s * a.ys + (size_t)ry * P + i;
+                nPh.y = a.in.pey[q];
+                nPh.z = a.in.phx[q];
+            }
+            if (xp) {
+                const size_t q = (size_t)s * a.xs + (size_t)r * a.W + cx;
+                nPh.x = a.in.pex[q];
+                nPh.w = a.in.phy[q];
+            }
         }
     };
     load(y0 - K);
@@ -609,53 +406,91 @@ __global__ __launch_bounds__(64) void k_adj_lean(AdjStreamArgs a) {
         constexpr int p = decltype(pc)::value, q = 1 - p;
         const int r = y0 - K + t;
         L_[q][0] = nL; Ca_[q][0] = nCa; Cs_[q][0] = nCs; Hx_[q][0] = nHx; Hy_[q][0] = nHy;
+        ph0[q] = nPh;
         load(r + 1);
 #pragma unroll
         for (int l = 0; l < K; ++l) {
+            if (TAIL && l >= nlev) continue;
+            const bool last = TAIL ? l == nlev - 1 : l == K - 1;
             const int j = r - 1 - l;
             const int n = a.n_top - 1 - l;
             const float en = en_pf[l];
             en_pf[l] = loadE(l, j + 1);
             const float pL = L_[p][l], pCa = Ca_[p][l], pCs = Cs_[p][l];
             const bool jown = j >= y0 && j < y1;
-            if (a.src_adjoint && own && jown && j == sj && i == si)
+            if (a.src_adjoint && w.own && jown && j == sj && i == si)
                 a.src_adjoint[(size_t)s * a.nt + n] = -pCs * pL * a.src_scale;
-            // transposed E step, then transposed H step
+            const int ry = yrow(j, NY, npml), ry1 = yrow(j + 1, NY, npml);
+            const bool yp = ry >= 0, yp1 = ry1 >= 0;
+            const RowPml rp = yp ? row_pml(a.p, j, ch, rdy) : r0;
+            const RowPml rp1 = yp1 ? row_pml(a.p, j + 1, ch, rdy) : r0;
+            float4 ph = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (yp || xp) ph = l == 0 ? ph0[p] : ring[j & (K - 1)][lane];
+            // A1: transposed E step, row j and the LDy of row j+1
             const float g = pCs * pL;
-            const float ldx = g * cxE;
+            const float tx = ph.x + g, ty = ph.y - g;
+            const float ldx = g * c.cxE + c.aEx * tx;
+            const float ldy = -g * rp.cyE + rp.aEy * ty;
+            if (xp) ph.x = c.bEx * tx;
+            if (yp) ph.y = rp.bEy * ty;
+            const float gn = Cs_[q][l] * L_[q][l];
+            float ldyn = -gn * rp1.cyE;
+            if (yp1) {
+                const float pey1 = l == 0 ? ph0[q].y : ring[(j + 1) & (K - 1)][lane].y;
+                ldyn += rp1.aEy * (pey1 - gn);
+            }
             const float lhy = Hy_[p][l] + (ldx - from_right(ldx));
-            const float lhx = Hx_[p][l] + (Cs_[q][l] * L_[q][l] - g) * cyE;
-            const float ldex = lhy * chx;
-            const float ldey = -lhx * chy;
+            const float lhx = Hx_[p][l] + (ldy - ldyn);
+            // A2: transposed H step
+            const float t1 = ph.w + ch * lhy;
+            const float ldex = lhy * c.chx + c.aHx * t1;
+            if (xp) ph.w = c.bHx * t1;
+            const float t2 = ph.z - ch * lhx;
+            const float ldey = -lhx * rp.chy + rp.aHy * t2;
+            if (yp) ph.z = rp.bHy * t2;
             float le = pCa * pL + (from_left(ldex) - ldex) + (ldey_prev[l] - ldey);
             ldey_prev[l] = ldey;
-            // adjoint source of step n
+            // A3: adjoint source of step n
             if (j >= rlo && j <= rhi) {
                 int lo, hi;
-                rec_range(a.g, s, NY, a.R, j, x0 - K, x0 - K + 64, lo, hi);
+                rec_range(a.g, s, NY, a.R, j, w.x0 - K, w.x0 - K + 64, lo, hi);
                 const float *res = a.residual + ((size_t)s * a.nt + n) * a.R;
                 for (int q2 = lo; q2 < hi; ++q2)
                     if (a.g.rcol[(size_t)s * a.R + q2] == i) le += res[a.g.ridx[(size_t)s * a.R + q2]];
             }
             // imaging
-            float2 acc = l == 0 ? make_float2(0.f, 0.f) : ring[j & (K - 1)][lane];
+            float2 acc = l == 0 ? make_float2(0.f, 0.f) : img[j & (K - 1)][lane];
             acc.x += en * (le - pL);
             acc.y += en * (le + pL);
             if (l + 1 < K) {
-                ring[j & (K - 1)][lane] = acc;
                 L_[q][l + 1] = le; Ca_[q][l + 1] = pCa; Cs_[q][l + 1] = pCs;
                 Hx_[q][l + 1] = lhx; Hy_[q][l + 1] = lhy;
-            } else if (jown && own) {
+                if (!last) {
+                    img[j & (K - 1)][lane] = acc;
+                    if (yp || xp) ring[j & (K - 1)][lane] = ph;
+                }
+            }
+            if (last && jown && w.own) {
                 const size_t k = (size_t)j * P + i;
                 a.out.E[so + k] = le;
                 a.out.Hx[so + k] = lhx;
                 a.out.Hy[so + k] = lhy;
                 a.S1[so + k] += acc.x;
                 a.S2[so + k] += acc.y;
+                if (yp) {
+                    const size_t q2 = (size_t)s * a.ys + (size_t)ry * P + i;
+                    a.out.pey[q2] = ph.y;
+                    a.out.phx[q2] = ph.z;
+                }
+                if (xp) {
+                    const size_t q2 = (size_t)s * a.xs + (size_t)j * a.W + cx;
+                    a.out.pex[q2] = ph.x;
+                    a.out.phy[q2] = ph.w;
+                }
             }
         }
     };
-    const int T = (y1 - y0) + 2 * K;
+    const int T = (y1 - y0) + K + nlev;
     for (int t = 0; t < T; t += 2) {
         iter(std::integral_constant<int, 0>(), t);
         iter(std::integral_constant<int, 1>(), t + 1);
@@ -664,31 +499,21 @@ __global__ __launch_bounds__(64) void k_adj_lean(AdjStreamArgs a) {
 
 }  // namespace
 
-hipError_t launch_fwd_lean(const FwdStreamArgs &a, hipStream_t st) {
-    const unsigned nb = (unsigned)a.S * (a.tl.lean_s1 - a.tl.lean_s0) *
-                        (a.tl.lean_b1 - a.tl.lean_b0);
-    if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fwd_lean<kStreamK>, dim3(nb), dim3(64), 0, st, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_adj_lean(const AdjStreamArgs &a, hipStream_t st) {
-    const unsigned nb = (unsigned)a.S * (a.tl.lean_s1 - a.tl.lean_s0) *
-                        (a.tl.lean_b1 - a.tl.lean_b0);
-    if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_adj_lean<kStreamK>, dim3(nb), dim3(64), 0, st, a);
-    return hipGetLastError();
-}
-
 hipError_t launch_fwd_stream(const FwdStreamArgs &a, hipStream_t st) {
     const unsigned nb = (unsigned)a.S * a.tl.nstrip * a.tl.nband;
-    hipLaunchKernelGGL(k_fwd_stream<kStreamK>, dim3(nb), dim3(64), 0, st, a);
+    if (a.nlev == kStreamK)
+        hipLaunchKernelGGL((k_fwd<kStreamK, false>), dim3(nb), dim3(64), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_fwd<kStreamK, true>), dim3(nb), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_adj_stream(const AdjStreamArgs &a, hipStream_t st) {
     const unsigned nb = (unsigned)a.S * a.tl.nstrip * a.tl.nband;
-    hipLaunchKernelGGL(k_adj_stream<kStreamK>, dim3(nb), dim3(64), 0, st, a);
+    if (a.nlev == kStreamK)
+        hipLaunchKernelGGL((k_adj<kStreamK, false>), dim3(nb), dim3(64), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_adj<kStreamK, true>), dim3(nb), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 
