@@ -145,6 +145,7 @@ int make_layout(const Dims &d, int mode, Layout &L) {
     L.off_ridx = take(S * d.R * sizeof(int));
     L.off_rspan = take(S * 2 * sizeof(int));
     L.off_bands = take(sizeof(L.bands));
+    L.off_cold = take(sizeof(StreamCold));
     L.state_bytes = align_up(field) * 2 + align_up(xs) * 2 + align_up(ys) * 2;
     L.off_fwd[0] = take(L.state_bytes);
     L.off_fwd[1] = take(L.state_bytes);
@@ -301,7 +302,8 @@ struct Timer {
 // Geometry to the device: sources, and per shot the receivers sorted by
 // (row, column) - stable in receiver index, so receivers sharing a cell stay
 // in index order - with a row CSR.
-int upload_geometry(const Ptrs &P, const fwi_geom *g, hipStream_t st) {
+int upload_geometry(const Ptrs &P, const fwi_geom *g, const StreamCold &cold,
+                    hipStream_t st) {
     const Dims &d = P.L->d;
     const size_t S = d.S, R = d.R, NY = d.NY;
     std::vector<int> rrow(S * (NY + 1)), rcol(S * R), ridx(S * R), rspan(S * 2);
@@ -335,6 +337,8 @@ int upload_geometry(const Ptrs &P, const fwi_geom *g, hipStream_t st) {
     FWI_TRY(hipMemcpyAsync(P.i(P.L->off_rspan), rspan.data(), rspan.size() * sizeof(int),
                            hipMemcpyHostToDevice, st));
     FWI_TRY(hipMemcpyAsync(P.i(P.L->off_bands), P.L->bands, sizeof(P.L->bands),
+                           hipMemcpyHostToDevice, st));
+    FWI_TRY(hipMemcpyAsync(P.base + P.L->off_cold, &cold, sizeof(StreamCold),
                            hipMemcpyHostToDevice, st));
     // pageable host sources: make sure the copies consumed them before the
     // vectors go out of scope
@@ -375,24 +379,39 @@ Tiling tiling(const Ptrs &P) {
     return t;
 }
 
-StreamGeom stream_geom(const Ptrs &P, const fwi_geom *g) {
-    StreamGeom sg;
-    sg.src_ij = P.i(P.L->off_src);
-    sg.wavelet = g->wavelet;
-    sg.rrow = P.i(P.L->off_rrow);
-    sg.rcol = P.i(P.L->off_rcol);
-    sg.ridx = P.i(P.L->off_ridx);
-    sg.rspan = P.i(P.L->off_rspan);
-    return sg;
+// The per-call cold arguments of the stencil kernels (see StreamCold).
+StreamCold make_cold(const Ptrs &P, const fwi_geom *g, float *traces,
+                     const float *residual, float *src_adjoint) {
+    const Layout &L = *P.L;
+    StreamCold c;
+    c.p = P.prof();
+    c.fs[0] = P.state(L.off_fwd[0], false);
+    c.fs[1] = P.state(L.off_fwd[1], false);
+    if (L.mode != FWI_SAVE_NONE) {
+        c.as[0] = P.state(L.off_adj[0], true);
+        c.as[1] = P.state(L.off_adj[1], true);
+    } else {
+        c.as[0] = c.as[1] = State{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    }
+    c.g.src_ij = P.i(L.off_src);
+    c.g.wavelet = g->wavelet;
+    c.g.rrow = P.i(L.off_rrow);
+    c.g.rcol = P.i(L.off_rcol);
+    c.g.ridx = P.i(L.off_ridx);
+    c.g.rspan = P.i(L.off_rspan);
+    c.traces = traces;
+    c.residual = residual;
+    c.src_adjoint = src_adjoint;
+    return c;
 }
 
-FwdStreamArgs fwd_args(const Ptrs &P, const fwi_geom *g) {
+FwdStreamArgs fwd_args(const Ptrs &P) {
     const Layout &L = *P.L;
     const Dims &d = L.d;
     FwdStreamArgs a;
     a.NX = d.NX; a.NY = d.NY; a.npml = d.npml; a.pitch = d.pitch;
-    a.W = d.W; a.Hs = d.Hs; a.S = d.S; a.R = d.R; a.nt = d.nt;
-    a.n = 0; a.nlev = 0;
+    a.W = d.W; a.S = d.S; a.R = d.R; a.nt = d.nt;
+    a.n = 0; a.nlev = 0; a.cur = 0; a.record = 0;
     a.tl = tiling(P);
     a.plane = d.plane; a.xs = d.xs; a.ys = d.ys;
     a.lev_stride = (size_t)d.S * d.plane;
@@ -402,18 +421,18 @@ FwdStreamArgs fwd_args(const Ptrs &P, const fwi_geom *g) {
     a.src_scale = (float)(1.0 / (d.dx * d.dy));
     a.Ca = P.f(L.off_Ca);
     a.Cs = P.f(L.off_Cs);
-    a.p = P.prof();
     a.E_in = nullptr; a.E_out = nullptr; a.E_lev = nullptr;
-    a.traces = nullptr;
-    a.g = stream_geom(P, g);
+    a.Hx_in = a.Hy_in = nullptr;
+    a.Hx_out = a.Hy_out = nullptr;
+    a.cold = reinterpret_cast<const StreamCold *>(P.base + L.off_cold);
     return a;
 }
 
-// Coefficients, profiles, geometry.
-int setup(const Ptrs &P, const fwi_geom *g, const float *eps_r, const float *sigma,
-          hipStream_t st) {
+// Coefficients, profiles, geometry and the cold arguments.
+int setup(const Ptrs &P, const fwi_geom *g, const StreamCold &cold, const float *eps_r,
+          const float *sigma, hipStream_t st) {
     const Dims &d = P.L->d;
-    int rc = upload_geometry(P, g, st);
+    int rc = upload_geometry(P, g, cold, st);
     if (rc != FWI_OK) return rc;
     FWI_TRY(launch_coefficients(eps_r, sigma, P.f(P.L->off_Ca), P.f(P.L->off_Cs), d.NX,
                                 d.NY, d.pitch, d.dt, st));
@@ -427,10 +446,10 @@ int setup(const Ptrs &P, const fwi_geom *g, const float *eps_r, const float *sig
 // The H / CPML state ping-pongs between fwd[cur] and fwd[cur ^ 1].
 template <class EIn, class EOut, class ELev>
 int forward_passes(const Ptrs &P, FwdStreamArgs a, int n0, int n1, int &cur, EIn ein,
-                   EOut eout, ELev elev, float *traces, hipStream_t st, Timer &tm) {
+                   EOut eout, ELev elev, bool record, hipStream_t st, Timer &tm) {
     const Layout &L = *P.L;
     State fs[2] = {P.state(L.off_fwd[0], false), P.state(L.off_fwd[1], false)};
-    a.traces = traces;
+    a.record = record ? 1 : 0;
     const double all = (double)L.d.NX * L.d.NY * L.d.S;
     for (int n = n0; n < n1; n += kStreamK) {
         a.n = n;
@@ -438,32 +457,36 @@ int forward_passes(const Ptrs &P, FwdStreamArgs a, int n0, int n1, int &cur, EIn
         a.E_in = ein(n);
         a.E_lev = elev(n);
         a.E_out = a.E_lev ? nullptr : eout(n);
-        a.in = fs[cur];
-        a.out = fs[cur ^ 1];
+        a.cur = cur;
+        a.Hx_in = fs[cur].Hx;
+        a.Hy_in = fs[cur].Hy;
+        a.Hx_out = fs[cur ^ 1].Hx;
+        a.Hy_out = fs[cur ^ 1].Hy;
         FWI_TRY(tm.run(K_FWD, all * a.nlev, [&] { return launch_fwd_stream(a, st); }));
         cur ^= 1;
     }
     return FWI_OK;
 }
 
-int do_forward(const Layout &L, const fwi_geom *g, const float *eps_r,
-               const float *sigma, float *traces, void *ws, hipStream_t st,
+int do_forward(const Layout &L, const fwi_geom *g, const StreamCold &cold,
+               const float *eps_r, const float *sigma, void *ws, hipStream_t st,
                Timer &tm) {
     const Dims &d = L.d;
     Ptrs P{static_cast<char *>(ws), &L};
-    int rc = setup(P, g, eps_r, sigma, st);
+    int rc = setup(P, g, cold, eps_r, sigma, st);
     if (rc != FWI_OK) return rc;
     State fs0 = P.state(L.off_fwd[0], false);
     rc = zero_state(fs0, d, false, st);
     if (rc != FWI_OK) return rc;
     FWI_TRY(launch_fill(P.slot(0), (size_t)d.S * d.plane, 0.f, st));
-    FwdStreamArgs a = fwd_args(P, g);
+    FwdStreamArgs a = fwd_args(P);
+    const bool record = cold.traces != nullptr;
     int cur = 0;
     if (L.mode == FWI_SAVE_HISTORY) {
         return forward_passes(
             P, a, 0, d.nt, cur, [&](int n) { return P.slot(n); },
             [&](int) { return (float *)nullptr; }, [&](int n) { return P.slot(n + 1); },
-            traces, st, tm);
+            record, st, tm);
     }
     // E ping-pongs between slots 0 and 1 pass by pass; with checkpoints, the
     // full state (E, H, CPML memories) is copied out every K steps
@@ -486,15 +509,14 @@ int do_forward(const Layout &L, const fwi_geom *g, const float *eps_r,
                 e ^= 1;
                 return P.slot(e);
             },
-            [&](int) { return (float *)nullptr; }, traces, st, tm);
+            [&](int) { return (float *)nullptr; }, record, st, tm);
         if (rc != FWI_OK) return rc;
     }
     return FWI_OK;
 }
 
-int do_adjoint(const Layout &L, const fwi_geom *g, const float *eps_r,
-               const float *sigma, const float *residual, float *g_eps,
-               float *g_sig, float *src_adj, void *ws, hipStream_t st, Timer &tm) {
+int do_adjoint(const Layout &L, const float *eps_r, const float *sigma, float *g_eps,
+               float *g_sig, void *ws, hipStream_t st, Timer &tm) {
     const Dims &d = L.d;
     Ptrs P{static_cast<char *>(ws), &L};
     State as[2] = {P.state(L.off_adj[0], true), P.state(L.off_adj[1], true)};
@@ -507,7 +529,7 @@ int do_adjoint(const Layout &L, const fwi_geom *g, const float *eps_r,
 
     AdjStreamArgs a;
     a.NX = d.NX; a.NY = d.NY; a.npml = d.npml; a.pitch = d.pitch;
-    a.W = d.W; a.Hs = d.Hs; a.S = d.S; a.R = d.R; a.nt = d.nt;
+    a.W = d.W; a.S = d.S; a.R = d.R; a.nt = d.nt;
     a.tl = tiling(P);
     a.plane = d.plane; a.xs = d.xs; a.ys = d.ys;
     a.lev_stride = field;
@@ -517,25 +539,25 @@ int do_adjoint(const Layout &L, const fwi_geom *g, const float *eps_r,
     a.src_scale = (float)(1.0 / (d.dx * d.dy));
     a.Ca = P.f(L.off_Ca);
     a.Cs = P.f(L.off_Cs);
-    a.p = P.prof();
     a.S1 = S1;
     a.S2 = S2;
-    a.residual = residual;
-    a.src_adjoint = src_adj;
-    a.src_ij = P.i(L.off_src);
-    a.g = stream_geom(P, g);
+    a.cold = reinterpret_cast<const StreamCold *>(P.base + L.off_cold);
     int acur = 0;
-    // adjoint passes over steps [n_lo, n_hi), the forward Ez^{n_lo + k} in slot k
     const double all = (double)d.NX * d.NY * d.S;
+    // adjoint passes over steps [n_lo, n_hi), the forward Ez^{n_lo + k} in slot k
     auto adj_range = [&](int n_hi, int n_lo) -> int {
         for (int n_top = n_hi; n_top > n_lo; n_top -= kStreamK) {
             a.nlev = std::min(kStreamK, n_top - n_lo);
             a.n_top = n_top;
             a.n_base = n_lo;
-            a.E_top = P.slot(n_top - n_lo);
             a.E_lev = P.slot(0);
-            a.in = as[acur];
-            a.out = as[acur ^ 1];
+            a.cur = acur;
+            a.L_in = as[acur].E;
+            a.LHx_in = as[acur].Hx;
+            a.LHy_in = as[acur].Hy;
+            a.L_out = as[acur ^ 1].E;
+            a.LHx_out = as[acur ^ 1].Hx;
+            a.LHy_out = as[acur ^ 1].Hy;
             FWI_TRY(tm.run(K_ADJ, all * a.nlev, [&] { return launch_adj_stream(a, st); }));
             acur ^= 1;
         }
@@ -548,7 +570,7 @@ int do_adjoint(const Layout &L, const fwi_geom *g, const float *eps_r,
     } else {
         // segment by segment, last first: restore the checkpoint, re-run the
         // segment forward into slots 0..K, then run the adjoint through it
-        FwdStreamArgs fa = fwd_args(P, g);
+        FwdStreamArgs fa = fwd_args(P);
         const size_t f = field * sizeof(float);
         for (int c = L.ncp - 1; c >= 0; --c) {
             const int n0 = c * L.K, n1 = std::min(d.nt, n0 + L.K);
@@ -560,7 +582,7 @@ int do_adjoint(const Layout &L, const fwi_geom *g, const float *eps_r,
             rc = forward_passes(
                 P, fa, n0, n1, cur, [&](int n) { return P.slot(n - n0); },
                 [&](int) { return (float *)nullptr; },
-                [&](int n) { return P.slot(n + 1 - n0); }, nullptr, st, tm);
+                [&](int n) { return P.slot(n + 1 - n0); }, false, st, tm);
             if (rc != FWI_OK) return rc;
             rc = adj_range(n1, n0);
             if (rc != FWI_OK) return rc;
@@ -622,7 +644,9 @@ extern "C" int fdtd_forward(const fwi_grid *grid, const fwi_geom *geom,
     int rc = prepare(grid, geom, save_mode, ws, ws_bytes, L);
     if (rc != FWI_OK) return rc;
     Timer tm;
-    return do_forward(L, geom, eps_r, sigma, traces, ws, static_cast<hipStream_t>(stream), tm);
+    Ptrs P{static_cast<char *>(ws), &L};
+    const StreamCold cold = make_cold(P, geom, traces, nullptr, nullptr);
+    return do_forward(L, geom, cold, eps_r, sigma, ws, static_cast<hipStream_t>(stream), tm);
 }
 
 extern "C" int fdtd_adjoint(const fwi_grid *grid, const fwi_geom *geom,
@@ -638,11 +662,11 @@ extern "C" int fdtd_adjoint(const fwi_grid *grid, const fwi_geom *geom,
     if (rc != FWI_OK) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     Ptrs P{static_cast<char *>(ws), &L};
-    rc = upload_geometry(P, geom, st);
+    const StreamCold cold = make_cold(P, geom, nullptr, residual, src_adjoint);
+    rc = upload_geometry(P, geom, cold, st);
     if (rc != FWI_OK) return rc;
     Timer tm;
-    return do_adjoint(L, geom, eps_r, sigma, residual, grad_eps_r, grad_sigma,
-                      src_adjoint, ws, st, tm);
+    return do_adjoint(L, eps_r, sigma, grad_eps_r, grad_sigma, ws, st, tm);
 }
 
 extern "C" int fwi_gradient_timed(const fwi_grid *grid, const fwi_geom *geom,
@@ -664,17 +688,16 @@ extern "C" int fwi_gradient_timed(const fwi_grid *grid, const fwi_geom *geom,
     tm.t = timing;
     tm.st = st;
     float *traces = traces_out ? traces_out : P.f(L.off_trc);
-    rc = do_forward(L, geom, eps_r, sigma, traces, ws, st, tm);
+    float *res = P.f(L.off_res);
+    const StreamCold cold = make_cold(P, geom, traces, res, nullptr);
+    rc = do_forward(L, geom, cold, eps_r, sigma, ws, st, tm);
     if (rc == FWI_OK) {
         const size_t ntr = (size_t)d.S * d.nt * d.R;
-        float *res = P.f(L.off_res);
         if (launch_residual_misfit(traces, observed, res, ntr,
                                    reinterpret_cast<double *>(P.base + L.off_mis), misfit,
                                    st) != hipSuccess)
             rc = FWI_EHIP;
-        if (rc == FWI_OK)
-            rc = do_adjoint(L, geom, eps_r, sigma, res, grad_eps_r, grad_sigma, nullptr, ws,
-                            st, tm);
+        if (rc == FWI_OK) rc = do_adjoint(L, eps_r, sigma, grad_eps_r, grad_sigma, ws, st, tm);
     }
     const int rc2 = tm.finish();
     return rc != FWI_OK ? rc : rc2;

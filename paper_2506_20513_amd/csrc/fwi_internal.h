@@ -64,7 +64,7 @@ struct Layout {
     int nstrip, nband;
     int bands[64];
     size_t off_Ca, off_Cs, off_prof;
-    size_t off_src, off_rrow, off_rcol, off_ridx, off_rspan, off_bands;
+    size_t off_src, off_rrow, off_rcol, off_ridx, off_rspan, off_bands, off_cold;
     size_t off_fwd[2];
     size_t off_slots;
     size_t off_ckpt, ckpt_stride;
@@ -98,38 +98,52 @@ struct Tiling {
     int nstrip, nband;
 };
 
+// Per-call constants of the stencil kernels that only rare branches read
+// (CPML rows and columns, receiver rows, the source row).  It lives in the
+// workspace, so the kernels load these pointers only where they need them
+// instead of holding them in scalar registers for the whole sweep.
+struct StreamCold {
+    Profiles p;
+    State fs[2];              // forward H / CPML states (E unused)
+    State as[2];              // adjoint states
+    StreamGeom g;
+    float *traces;            // [S][nt][R] or null
+    const float *residual;    // [S][nt][R]
+    float *src_adjoint;       // [S][nt] or null
+};
+
+// Hot arguments of one forward pass: steps n .. n+nlev-1.
 struct FwdStreamArgs {
-    int NX, NY, npml, pitch, W, Hs, S, R, nt;
+    int NX, NY, npml, pitch, W, S, R, nt;
     int n, nlev;              // first step of the pass, steps in the pass (<= K)
+    int cur;                  // input state cold->fs[cur], output fs[cur ^ 1]
+    int record;               // write traces
     Tiling tl;
     size_t plane, xs, ys, lev_stride;
     float ch, rdx, rdy, src_scale;
     const float *Ca, *Cs;
-    Profiles p;
     const float *E_in;        // Ez^n, all shots
     float *E_out;             // Ez^{n+nlev} (unused when E_lev is set)
     float *E_lev;             // or null: Ez^{n+l+1} to E_lev + l * lev_stride
-    State in, out;            // H and CPML memories, n-1/2 -> n+nlev-1/2
-    float *traces;            // [S][nt][R] or null
-    StreamGeom g;
+    const float *Hx_in, *Hy_in;
+    float *Hx_out, *Hy_out;
+    const StreamCold *cold;
 };
 
+// Hot arguments of one adjoint pass: steps n_top-1 .. n_top-nlev.
 struct AdjStreamArgs {
-    int NX, NY, npml, pitch, W, Hs, S, R, nt;
-    int n_top, n_base, nlev;  // pass covers steps n_top-1 .. n_top-nlev
+    int NX, NY, npml, pitch, W, S, R, nt;
+    int n_top, n_base, nlev;
+    int cur;                  // input state cold->as[cur], output as[cur ^ 1]
     Tiling tl;
     size_t plane, xs, ys, lev_stride;
     float ch, rdx, rdy, src_scale;
     const float *Ca, *Cs;
-    Profiles p;
-    const float *E_top;       // forward Ez^{n_top}
     const float *E_lev;       // forward Ez^{n_base + k} at E_lev + k * lev_stride
-    State in, out;            // lambda^{n_top} -> lambda^{n_top-nlev}
+    const float *L_in, *LHx_in, *LHy_in;
+    float *L_out, *LHx_out, *LHy_out;
     float *S1, *S2;           // per-shot correlation sums [S][NY][pitch]
-    const float *residual;    // [S][nt][R]
-    float *src_adjoint;       // [S][nt] or null
-    const int *src_ij;
-    StreamGeom g;
+    const StreamCold *cold;
 };
 
 // ---- launchers ---------------------------------------------------------------

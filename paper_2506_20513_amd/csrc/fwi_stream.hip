@@ -127,10 +127,13 @@ __device__ __forceinline__ ColPml col_pml(const Profiles &p, int i, bool inx, fl
 
 struct WaveTile {
     int s, x0, i, y0, y1;
-    bool inx, own;
+    bool inx, own, edge;
 };
+// Wave -> (shot, strip, band).  An edge strip has lanes in a CPML column or
+// outside the grid; interior strips take the specialised path (kappa = 1,
+// no CPML memory, no bounds test).
 template <int K>
-__device__ __forceinline__ WaveTile wave_tile(const Tiling &tl, int S, int NX) {
+__device__ __forceinline__ WaveTile wave_tile(const Tiling &tl, int S, int NX, int npml) {
     constexpr int OW = 64 - 2 * K;
     WaveTile w;
     const int wid = xcd_logical(blockIdx.x, gridDim.x);
@@ -143,6 +146,7 @@ __device__ __forceinline__ WaveTile wave_tile(const Tiling &tl, int S, int NX) {
     w.own = (int)threadIdx.x >= K && (int)threadIdx.x < K + OW && w.inx;
     w.y0 = tl.bands[band];
     w.y1 = tl.bands[band + 1];
+    w.edge = !(w.x0 - K >= npml && w.x0 - K + 63 <= NX - 2 - npml);
     return w;
 }
 
@@ -158,28 +162,35 @@ __device__ __forceinline__ WaveTile wave_tile(const Tiling &tl, int S, int NX) {
 // H rows/columns that the E update never reads (Hx at j = NY-1, Hy at
 // i = NX-1) see a zero difference and stay zero, and ring Ez stays zero.
 // psi is a float4 (psi_hx, psi_hy, psi_ex, psi_ey).
-template <int K, bool TAIL>
-__global__ __launch_bounds__(64) void k_fwd(FwdStreamArgs a) {
-    static_assert((K & (K - 1)) == 0, "K must be a power of two");
+template <int K, bool EDGE, bool TAIL>
+__device__ __forceinline__ void fwd_body(const FwdStreamArgs &a, const WaveTile &w,
+                                         float4 (*ring)[64]) {
     constexpr int OW = 64 - 2 * K;
-    __shared__ float4 ring[K][64];
+    const StreamCold *__restrict__ cold = a.cold;
     const int lane = threadIdx.x;
-    const WaveTile w = wave_tile<K>(a.tl, a.S, a.NX);
     const int s = w.s, i = w.i, y0 = w.y0, y1 = w.y1;
     const int NY = a.NY, P = a.pitch, npml = a.npml;
     const int nlev = TAIL ? a.nlev : K;
-    const int cx = w.inx ? xcol(i, a.NX, npml) : -1;
-    const bool xp = cx >= 0;
+    const bool inx = EDGE ? w.inx : true;
+    const bool own = w.own;
+    const int cx = EDGE && inx ? xcol(i, a.NX, npml) : -1;
+    const bool xp = EDGE && cx >= 0;
     const float ch = a.ch, rdx = a.rdx, rdy = a.rdy;
-    const ColPml c = col_pml(a.p, i, w.inx, ch, rdx);
+    ColPml c;
+    if (EDGE) {
+        c = col_pml(cold->p, i, inx, ch, rdx);
+    } else {
+        c = ColPml{ch * rdx, rdx, 0.f, 0.f, 0.f, 0.f};
+    }
     const RowPml r0{ch * rdy, rdy, 0.f, 0.f, 0.f, 0.f};
-    const int si = a.g.src_ij[2 * s], sj = a.g.src_ij[2 * s + 1];
-    const int rlo = a.g.rspan[2 * s], rhi = a.g.rspan[2 * s + 1];
+    const int si = cold->g.src_ij[2 * s], sj = cold->g.src_ij[2 * s + 1];
+    const int rlo = cold->g.rspan[2 * s], rhi = cold->g.rspan[2 * s + 1];
     const size_t so = (size_t)s * a.plane;
     const float *__restrict__ Ein = a.E_in + so;
-    const float *__restrict__ Hxin = a.in.Hx + so;
-    const float *__restrict__ Hyin = a.in.Hy + so;
-    const float *__restrict__ wav = a.g.wavelet + (size_t)s * a.nt + a.n;
+    const float *__restrict__ Hxin = a.Hx_in + so;
+    const float *__restrict__ Hyin = a.Hy_in + so;
+    const float *__restrict__ Cap = a.Ca;
+    const float *__restrict__ Csp = a.Cs;
     const int rlast = min(NY - 1, y1 + nlev - 1);
 
 #pragma unroll
@@ -198,23 +209,25 @@ __global__ __launch_bounds__(64) void k_fwd(FwdStreamArgs a) {
     auto load = [&](int r) {
         nE = nHx = nHy = nCa = nCs = 0.f;
         nPs = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (r >= 0 && r <= rlast && w.inx) {
+        if (r >= 0 && r <= rlast && inx) {
             const size_t k = (size_t)r * P + i;
             nE = Ein[k];
             nHx = Hxin[k];
             nHy = Hyin[k];
-            nCa = a.Ca[k];
-            nCs = a.Cs[k];
+            nCa = Cap[k];
+            nCs = Csp[k];
             const int ry = yrow(r, NY, npml);
             if (ry >= 0) {
+                const State &in = cold->fs[a.cur];
                 const size_t q = (size_t)s * a.ys + (size_t)ry * P + i;
-                nPs.x = a.in.phx[q];
-                nPs.w = a.in.pey[q];
+                nPs.x = in.phx[q];
+                nPs.w = in.pey[q];
             }
             if (xp) {
+                const State &in = cold->fs[a.cur];
                 const size_t q = (size_t)s * a.xs + (size_t)r * a.W + cx;
-                nPs.y = a.in.phy[q];
-                nPs.z = a.in.pex[q];
+                nPs.y = in.phy[q];
+                nPs.z = in.pex[q];
             }
         }
     };
@@ -234,17 +247,18 @@ __global__ __launch_bounds__(64) void k_fwd(FwdStreamArgs a) {
             const float pE = E_[p][l], pCa = Ca_[p][l], pCs = Cs_[p][l];
             const float hprev = (l + 1 < K) ? Hx_[p][l + 1] : hlast;
             const bool jown = j >= y0 && j < y1;
-            if (a.traces && jown && j >= rlo && j <= rhi) {    // stage 1
+            if (a.record && jown && j >= rlo && j <= rhi) {    // stage 1
+                const StreamGeom &g = cold->g;
                 int lo, hi;
-                rec_range(a.g, s, NY, a.R, j, w.x0, w.x0 + OW, lo, hi);
+                rec_range(g, s, NY, a.R, j, w.x0, w.x0 + OW, lo, hi);
                 for (int q2 = lo; q2 < hi; ++q2)
-                    if (w.own && a.g.rcol[(size_t)s * a.R + q2] == i)
-                        a.traces[((size_t)s * a.nt + a.n + l) * a.R +
-                                 a.g.ridx[(size_t)s * a.R + q2]] = pE;
+                    if (own && g.rcol[(size_t)s * a.R + q2] == i)
+                        cold->traces[((size_t)s * a.nt + a.n + l) * a.R +
+                                     g.ridx[(size_t)s * a.R + q2]] = pE;
             }
             const int ry = yrow(j, NY, npml);
             const bool yp = ry >= 0;
-            const RowPml rp = yp ? row_pml(a.p, j, ch, rdy) : r0;
+            const RowPml rp = yp ? row_pml(cold->p, j, ch, rdy) : r0;
             // stages 2-3: H to n+l+1/2
             const float dEy = E_[q][l] - pE;
             const float dEx = from_right(pE) - pE;
@@ -273,7 +287,8 @@ __global__ __launch_bounds__(64) void k_fwd(FwdStreamArgs a) {
                 curl -= ps.w;
             }
             float e = pCa * pE + pCs * curl;
-            if (j == sj && i == si) e -= pCs * wav[l] * a.src_scale;
+            if (j == sj && i == si)
+                e -= pCs * cold->g.wavelet[(size_t)s * a.nt + a.n + l] * a.src_scale;
             if (l + 1 < K) {
                 E_[q][l + 1] = e; Hx_[q][l + 1] = hx; Hy_[q][l + 1] = hy;
                 Ca_[q][l + 1] = pCa; Cs_[q][l + 1] = pCs;
@@ -281,22 +296,25 @@ __global__ __launch_bounds__(64) void k_fwd(FwdStreamArgs a) {
             } else {
                 hlast = hx;
             }
-            if (jown && w.own) {
+            if (jown && own) {
                 const size_t k = (size_t)j * P + i;
                 if (a.E_lev) a.E_lev[(size_t)l * a.lev_stride + so + k] = e;
                 if (last) {
                     if (!a.E_lev) a.E_out[so + k] = e;
-                    a.out.Hx[so + k] = hx;
-                    a.out.Hy[so + k] = hy;
-                    if (yp) {
-                        const size_t q2 = (size_t)s * a.ys + (size_t)ry * P + i;
-                        a.out.phx[q2] = ps.x;
-                        a.out.pey[q2] = ps.w;
-                    }
-                    if (xp) {
-                        const size_t q2 = (size_t)s * a.xs + (size_t)j * a.W + cx;
-                        a.out.phy[q2] = ps.y;
-                        a.out.pex[q2] = ps.z;
+                    a.Hx_out[so + k] = hx;
+                    a.Hy_out[so + k] = hy;
+                    if (yp || xp) {
+                        const State &out = cold->fs[a.cur ^ 1];
+                        if (yp) {
+                            const size_t q2 = (size_t)s * a.ys + (size_t)ry * P + i;
+                            out.phx[q2] = ps.x;
+                            out.pey[q2] = ps.w;
+                        }
+                        if (xp) {
+                            const size_t q2 = (size_t)s * a.xs + (size_t)j * a.W + cx;
+                            out.phy[q2] = ps.y;
+                            out.pex[q2] = ps.z;
+                        }
                     }
                 }
             }
@@ -307,6 +325,17 @@ __global__ __launch_bounds__(64) void k_fwd(FwdStreamArgs a) {
         iter(std::integral_constant<int, 0>(), t);
         iter(std::integral_constant<int, 1>(), t + 1);
     }
+}
+
+template <int K, bool TAIL>
+__global__ __launch_bounds__(64) void k_fwd(FwdStreamArgs a) {
+    static_assert((K & (K - 1)) == 0, "K must be a power of two");
+    __shared__ float4 ring[K][64];
+    const WaveTile w = wave_tile<K>(a.tl, a.S, a.NX, a.npml);
+    if (w.edge)
+        fwd_body<K, true, TAIL>(a, w, ring);
+    else
+        fwd_body<K, false, TAIL>(a, w, ring);
 }
 
 // ---------------------------------------------------------------------------
@@ -333,33 +362,40 @@ __global__ __launch_bounds__(64) void k_fwd(FwdStreamArgs a) {
 // with lambda^n the state after the adjoint source of step n, so a level
 // needs only the forward Ez^n of its own step (prefetched a row ahead); the
 // partial sums of the rows in flight live in a second LDS ring.
-template <int K, bool TAIL>
-__global__ __launch_bounds__(64) void k_adj(AdjStreamArgs a) {
-    static_assert((K & (K - 1)) == 0, "K must be a power of two");
-    __shared__ float4 ring[K][64];
-    __shared__ float2 img[K][64];
+template <int K, bool EDGE, bool TAIL>
+__device__ __forceinline__ void adj_body(const AdjStreamArgs &a, const WaveTile &w,
+                                         float4 (*ring)[64], float2 (*img)[64]) {
+    const StreamCold *__restrict__ cold = a.cold;
     const int lane = threadIdx.x;
-    const WaveTile w = wave_tile<K>(a.tl, a.S, a.NX);
     const int s = w.s, i = w.i, y0 = w.y0, y1 = w.y1;
     const int NY = a.NY, P = a.pitch, npml = a.npml;
     const int nlev = TAIL ? a.nlev : K;
-    const int cx = w.inx ? xcol(i, a.NX, npml) : -1;
-    const bool xp = cx >= 0;
+    const bool inx = EDGE ? w.inx : true;
+    const bool own = w.own;
+    const int cx = EDGE && inx ? xcol(i, a.NX, npml) : -1;
+    const bool xp = EDGE && cx >= 0;
     const float ch = a.ch, rdx = a.rdx, rdy = a.rdy;
-    const ColPml c = col_pml(a.p, i, w.inx, ch, rdx);
+    ColPml c;
+    if (EDGE) {
+        c = col_pml(cold->p, i, inx, ch, rdx);
+    } else {
+        c = ColPml{ch * rdx, rdx, 0.f, 0.f, 0.f, 0.f};
+    }
     const RowPml r0{ch * rdy, rdy, 0.f, 0.f, 0.f, 0.f};
-    const int si = a.src_ij[2 * s], sj = a.src_ij[2 * s + 1];
-    const int rlo = a.g.rspan[2 * s], rhi = a.g.rspan[2 * s + 1];
+    const int si = cold->g.src_ij[2 * s], sj = cold->g.src_ij[2 * s + 1];
+    const int rlo = cold->g.rspan[2 * s], rhi = cold->g.rspan[2 * s + 1];
     const size_t so = (size_t)s * a.plane;
-    const float *__restrict__ Lin = a.in.E + so;
-    const float *__restrict__ LHxin = a.in.Hx + so;
-    const float *__restrict__ LHyin = a.in.Hy + so;
-    const float *__restrict__ Ef = a.E_lev + so + (w.inx ? i : 0);
+    const float *__restrict__ Lin = a.L_in + so;
+    const float *__restrict__ LHxin = a.LHx_in + so;
+    const float *__restrict__ LHyin = a.LHy_in + so;
+    const float *__restrict__ Cap = a.Ca;
+    const float *__restrict__ Csp = a.Cs;
+    const float *__restrict__ Ef = a.E_lev + so + (inx ? i : 0);
     const int rlast = min(NY - 1, y1 + nlev - 1);
 
     // forward Ez^{n_l}(j) of level l (n_l = n_top - 1 - l), 0 off the grid
     auto loadE = [&](int l, int j) {
-        return (j >= 0 && j < NY && w.inx)
+        return (j >= 0 && j < NY && inx)
                    ? Ef[(size_t)(a.n_top - 1 - l - a.n_base) * a.lev_stride + (size_t)j * P]
                    : 0.f;
     };
@@ -380,23 +416,25 @@ __global__ __launch_bounds__(64) void k_adj(AdjStreamArgs a) {
     auto load = [&](int r) {
         nL = nCa = nCs = nHx = nHy = 0.f;
         nPh = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (r >= 0 && r <= rlast && w.inx) {
+        if (r >= 0 && r <= rlast && inx) {
             const size_t k = (size_t)r * P + i;
             nL = Lin[k];
             nHx = LHxin[k];
             nHy = LHyin[k];
-            nCa = a.Ca[k];
-            nCs = a.Cs[k];
+            nCa = Cap[k];
+            nCs = Csp[k];
             const int ry = yrow(r, NY, npml);
             if (ry >= 0) {
+                const State &in = cold->as[a.cur];
                 const size_t q = (size_t)s * a.ys + (size_t)ry * P + i;
-                nPh.y = a.in.pey[q];
-                nPh.z = a.in.phx[q];
+                nPh.y = in.pey[q];
+                nPh.z = in.phx[q];
             }
             if (xp) {
+                const State &in = cold->as[a.cur];
                 const size_t q = (size_t)s * a.xs + (size_t)r * a.W + cx;
-                nPh.x = a.in.pex[q];
-                nPh.w = a.in.phy[q];
+                nPh.x = in.pex[q];
+                nPh.w = in.phy[q];
             }
         }
     };
@@ -418,12 +456,12 @@ __global__ __launch_bounds__(64) void k_adj(AdjStreamArgs a) {
             en_pf[l] = loadE(l, j + 1);
             const float pL = L_[p][l], pCa = Ca_[p][l], pCs = Cs_[p][l];
             const bool jown = j >= y0 && j < y1;
-            if (a.src_adjoint && w.own && jown && j == sj && i == si)
-                a.src_adjoint[(size_t)s * a.nt + n] = -pCs * pL * a.src_scale;
+            if (jown && j == sj && cold->src_adjoint && own && i == si)
+                cold->src_adjoint[(size_t)s * a.nt + n] = -pCs * pL * a.src_scale;
             const int ry = yrow(j, NY, npml), ry1 = yrow(j + 1, NY, npml);
             const bool yp = ry >= 0, yp1 = ry1 >= 0;
-            const RowPml rp = yp ? row_pml(a.p, j, ch, rdy) : r0;
-            const RowPml rp1 = yp1 ? row_pml(a.p, j + 1, ch, rdy) : r0;
+            const RowPml rp = yp ? row_pml(cold->p, j, ch, rdy) : r0;
+            const RowPml rp1 = yp1 ? row_pml(cold->p, j + 1, ch, rdy) : r0;
             float4 ph = make_float4(0.f, 0.f, 0.f, 0.f);
             if (yp || xp) ph = l == 0 ? ph0[p] : ring[j & (K - 1)][lane];
             // A1: transposed E step, row j and the LDy of row j+1
@@ -452,11 +490,12 @@ __global__ __launch_bounds__(64) void k_adj(AdjStreamArgs a) {
             ldey_prev[l] = ldey;
             // A3: adjoint source of step n
             if (j >= rlo && j <= rhi) {
+                const StreamGeom &g2 = cold->g;
                 int lo, hi;
-                rec_range(a.g, s, NY, a.R, j, w.x0 - K, w.x0 - K + 64, lo, hi);
-                const float *res = a.residual + ((size_t)s * a.nt + n) * a.R;
+                rec_range(g2, s, NY, a.R, j, w.x0 - K, w.x0 - K + 64, lo, hi);
+                const float *res = cold->residual + ((size_t)s * a.nt + n) * a.R;
                 for (int q2 = lo; q2 < hi; ++q2)
-                    if (a.g.rcol[(size_t)s * a.R + q2] == i) le += res[a.g.ridx[(size_t)s * a.R + q2]];
+                    if (g2.rcol[(size_t)s * a.R + q2] == i) le += res[g2.ridx[(size_t)s * a.R + q2]];
             }
             // imaging
             float2 acc = l == 0 ? make_float2(0.f, 0.f) : img[j & (K - 1)][lane];
@@ -470,22 +509,25 @@ __global__ __launch_bounds__(64) void k_adj(AdjStreamArgs a) {
                     if (yp || xp) ring[j & (K - 1)][lane] = ph;
                 }
             }
-            if (last && jown && w.own) {
+            if (last && jown && own) {
                 const size_t k = (size_t)j * P + i;
-                a.out.E[so + k] = le;
-                a.out.Hx[so + k] = lhx;
-                a.out.Hy[so + k] = lhy;
+                a.L_out[so + k] = le;
+                a.LHx_out[so + k] = lhx;
+                a.LHy_out[so + k] = lhy;
                 a.S1[so + k] += acc.x;
                 a.S2[so + k] += acc.y;
-                if (yp) {
-                    const size_t q2 = (size_t)s * a.ys + (size_t)ry * P + i;
-                    a.out.pey[q2] = ph.y;
-                    a.out.phx[q2] = ph.z;
-                }
-                if (xp) {
-                    const size_t q2 = (size_t)s * a.xs + (size_t)j * a.W + cx;
-                    a.out.pex[q2] = ph.x;
-                    a.out.phy[q2] = ph.w;
+                if (yp || xp) {
+                    const State &out = cold->as[a.cur ^ 1];
+                    if (yp) {
+                        const size_t q2 = (size_t)s * a.ys + (size_t)ry * P + i;
+                        out.pey[q2] = ph.y;
+                        out.phx[q2] = ph.z;
+                    }
+                    if (xp) {
+                        const size_t q2 = (size_t)s * a.xs + (size_t)j * a.W + cx;
+                        out.pex[q2] = ph.x;
+                        out.phy[q2] = ph.w;
+                    }
                 }
             }
         }
@@ -495,6 +537,18 @@ __global__ __launch_bounds__(64) void k_adj(AdjStreamArgs a) {
         iter(std::integral_constant<int, 0>(), t);
         iter(std::integral_constant<int, 1>(), t + 1);
     }
+}
+
+template <int K, bool TAIL>
+__global__ __launch_bounds__(64) void k_adj(AdjStreamArgs a) {
+    static_assert((K & (K - 1)) == 0, "K must be a power of two");
+    __shared__ float4 ring[K][64];
+    __shared__ float2 img[K][64];
+    const WaveTile w = wave_tile<K>(a.tl, a.S, a.NX, a.npml);
+    if (w.edge)
+        adj_body<K, true, TAIL>(a, w, ring, img);
+    else
+        adj_body<K, false, TAIL>(a, w, ring, img);
 }
 
 }  // namespace
