@@ -92,6 +92,9 @@ extern "C" {
 #define FWI_SAVE_HISTORY 2     /* Ez at every step (small problems only)    */
 
 /* Grid, time axis and CPML parameters (all host values). */
+/* The total grid is NX = nx + 2 npml by NY = ny + 2 npml cells; each of NX
+ * and NY is 3 .. 2^20 and NY * round_up(NX, 64) below 2^30 cells, else
+ * FWI_EINVAL. */
 typedef struct fwi_grid {
     int32_t nx, ny;            /* interior cells, x (horizontal) and y (depth) */
     int32_t npml;              /* CPML cells on each side, >= 0                */

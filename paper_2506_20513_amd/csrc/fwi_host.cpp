@@ -26,6 +26,8 @@ int check_grid(const fwi_grid *g) {
     const int64_t NX = (int64_t)g->nx + 2 * (int64_t)g->npml;
     const int64_t NY = (int64_t)g->ny + 2 * (int64_t)g->npml;
     if (NX < 3 || NY < 3 || NX > (1 << 20) || NY > (1 << 20)) return FWI_EINVAL;
+    // the stencil kernels address one shot's plane with 32-bit byte offsets
+    if ((NX + 63) / 64 * 64 * NY >= ((int64_t)1 << 30)) return FWI_EINVAL;
     if (!finite_pos(g->dx) || !finite_pos(g->dy) || !finite_pos(g->dt)) return FWI_EINVAL;
     if (g->cpml_order < 1 || g->cpml_order > 16) return FWI_EINVAL;
     if (!std::isfinite(g->cpml_sigma_scale) || g->cpml_sigma_scale < 0.0) return FWI_EINVAL;

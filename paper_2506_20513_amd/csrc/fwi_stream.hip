@@ -34,6 +34,29 @@
 namespace fwi {
 namespace {
 
+// Memory access helpers.  Per-lane accesses go through the global address
+// space with a uniform base and a 32-bit offset (SGPR base + VGPR offset
+// addressing); read-only tables indexed by uniform values go through the
+// constant address space (scalar loads).  Offsets stay below 2^32 bytes by
+// the grid-size check on the host.
+#define FWI_AS_GLOBAL __attribute__((address_space(1)))
+#define FWI_AS_CONST __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ T ldg(const T *base, unsigned idx) {
+    return *(const FWI_AS_GLOBAL T *)((const FWI_AS_GLOBAL char *)base +
+                                      (size_t)(idx * (unsigned)sizeof(T)));
+}
+template <class T>
+__device__ __forceinline__ void stg(T *base, unsigned idx, T v) {
+    *(FWI_AS_GLOBAL T *)((FWI_AS_GLOBAL char *)base + (size_t)(idx * (unsigned)sizeof(T))) = v;
+}
+template <class T>
+__device__ __forceinline__ T ldc(const T *base, unsigned idx) {
+    return ((const FWI_AS_CONST T *)base)[idx];
+}
+// The per-call cold arguments, read with scalar loads.
+using ColdRef = const FWI_AS_CONST StreamCold *;
+
 // lane i receives lane i-1's value (lane 0 receives 0)
 __device__ __forceinline__ float from_left(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
@@ -70,22 +93,22 @@ __device__ __forceinline__ int xcd_logical(int b, int nb) {
 
 // Receivers of shot s on row j whose column lies in [c0, c1): index range
 // into the shot's (row, column)-sorted receiver list.
-__device__ __forceinline__ void rec_range(const StreamGeom &g, int s, int NY, int R, int j,
-                                          int c0, int c1, int &lo, int &hi) {
-    const int *rr = g.rrow + (size_t)s * (NY + 1);
-    lo = rr[j];
-    hi = rr[j + 1];
+__device__ __forceinline__ void rec_range(const int *rrow, const int *rcol, int s, int NY,
+                                          int R, int j, int c0, int c1, int &lo, int &hi) {
+    const int *rr = rrow + (size_t)s * (NY + 1);
+    lo = ldc(rr, j);
+    hi = ldc(rr, j + 1);
     if (lo == hi) return;
-    const int *rc = g.rcol + (size_t)s * R;
+    const int *rc = rcol + (size_t)s * R;
     int a = lo, b = hi;
     while (a < b) {
         const int m = (a + b) >> 1;
-        if (rc[m] < c0) a = m + 1; else b = m;
+        if (ldc(rc, m) < c0) a = m + 1; else b = m;
     }
     int e = a, f = hi;
     while (e < f) {
         const int m = (e + f) >> 1;
-        if (rc[m] < c1) e = m + 1; else f = m;
+        if (ldc(rc, m) < c1) e = m + 1; else f = m;
     }
     lo = a;
     hi = e;
@@ -96,14 +119,14 @@ __device__ __forceinline__ void rec_range(const StreamGeom &g, int s, int NY, in
 struct RowPml {
     float chy, cyE, bHy, aHy, bEy, aEy;
 };
-__device__ __forceinline__ RowPml row_pml(const Profiles &p, int j, float ch, float rdy) {
+__device__ __forceinline__ RowPml row_pml(ColdRef cold, int j, float ch, float rdy) {
     RowPml r;
-    r.chy = ch * rdy * p.kHy[j];
-    r.cyE = rdy * p.kEy[j];
-    r.bHy = p.bHy[j];
-    r.aHy = p.aHy[j] * rdy;
-    r.bEy = p.bEy[j];
-    r.aEy = p.aEy[j] * rdy;
+    r.chy = ch * rdy * ldc<float>(cold->p.kHy, j);
+    r.cyE = rdy * ldc<float>(cold->p.kEy, j);
+    r.bHy = ldc<float>(cold->p.bHy, j);
+    r.aHy = ldc<float>(cold->p.aHy, j) * rdy;
+    r.bEy = ldc<float>(cold->p.bEy, j);
+    r.aEy = ldc<float>(cold->p.aEy, j) * rdy;
     return r;
 }
 
@@ -111,16 +134,15 @@ __device__ __forceinline__ RowPml row_pml(const Profiles &p, int j, float ch, fl
 struct ColPml {
     float chx, cxE, bHx, aHx, bEx, aEx;
 };
-__device__ __forceinline__ ColPml col_pml(const Profiles &p, int i, bool inx, float ch,
-                                          float rdx) {
+__device__ __forceinline__ ColPml col_pml(ColdRef cold, int i, bool inx, float ch, float rdx) {
     ColPml c{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (inx) {
-        c.chx = ch * rdx * p.kHx[i];
-        c.cxE = rdx * p.kEx[i];
-        c.bHx = p.bHx[i];
-        c.aHx = p.aHx[i] * rdx;
-        c.bEx = p.bEx[i];
-        c.aEx = p.aEx[i] * rdx;
+        c.chx = ch * rdx * ldg<float>(cold->p.kHx, i);
+        c.cxE = rdx * ldg<float>(cold->p.kEx, i);
+        c.bHx = ldg<float>(cold->p.bHx, i);
+        c.aHx = ldg<float>(cold->p.aHx, i) * rdx;
+        c.bEx = ldg<float>(cold->p.bEx, i);
+        c.aEx = ldg<float>(cold->p.aEx, i) * rdx;
     }
     return c;
 }
@@ -166,7 +188,7 @@ template <int K, bool EDGE, bool TAIL>
 __device__ __forceinline__ void fwd_body(const FwdStreamArgs &a, const WaveTile &w,
                                          float4 (*ring)[64]) {
     constexpr int OW = 64 - 2 * K;
-    const StreamCold *__restrict__ cold = a.cold;
+    ColdRef cold = (ColdRef)a.cold;
     const int lane = threadIdx.x;
     const int s = w.s, i = w.i, y0 = w.y0, y1 = w.y1;
     const int NY = a.NY, P = a.pitch, npml = a.npml;
@@ -178,19 +200,19 @@ __device__ __forceinline__ void fwd_body(const FwdStreamArgs &a, const WaveTile 
     const float ch = a.ch, rdx = a.rdx, rdy = a.rdy;
     ColPml c;
     if (EDGE) {
-        c = col_pml(cold->p, i, inx, ch, rdx);
+        c = col_pml(cold, i, inx, ch, rdx);
     } else {
         c = ColPml{ch * rdx, rdx, 0.f, 0.f, 0.f, 0.f};
     }
     const RowPml r0{ch * rdy, rdy, 0.f, 0.f, 0.f, 0.f};
-    const int si = cold->g.src_ij[2 * s], sj = cold->g.src_ij[2 * s + 1];
-    const int rlo = cold->g.rspan[2 * s], rhi = cold->g.rspan[2 * s + 1];
+    const int si = ldc<int>(cold->g.src_ij, 2 * s), sj = ldc<int>(cold->g.src_ij, 2 * s + 1);
+    const int rlo = ldc<int>(cold->g.rspan, 2 * s), rhi = ldc<int>(cold->g.rspan, 2 * s + 1);
     const size_t so = (size_t)s * a.plane;
-    const float *__restrict__ Ein = a.E_in + so;
-    const float *__restrict__ Hxin = a.Hx_in + so;
-    const float *__restrict__ Hyin = a.Hy_in + so;
-    const float *__restrict__ Cap = a.Ca;
-    const float *__restrict__ Csp = a.Cs;
+    const float *Ein = a.E_in + so;
+    const float *Hxin = a.Hx_in + so;
+    const float *Hyin = a.Hy_in + so;
+    const float *Cap = a.Ca;
+    const float *Csp = a.Cs;
     const int rlast = min(NY - 1, y1 + nlev - 1);
 
 #pragma unroll
@@ -210,24 +232,22 @@ __device__ __forceinline__ void fwd_body(const FwdStreamArgs &a, const WaveTile 
         nE = nHx = nHy = nCa = nCs = 0.f;
         nPs = make_float4(0.f, 0.f, 0.f, 0.f);
         if (r >= 0 && r <= rlast && inx) {
-            const size_t k = (size_t)r * P + i;
-            nE = Ein[k];
-            nHx = Hxin[k];
-            nHy = Hyin[k];
-            nCa = Cap[k];
-            nCs = Csp[k];
+            const unsigned k = (unsigned)(r * P + i);
+            nE = ldg(Ein, k);
+            nHx = ldg(Hxin, k);
+            nHy = ldg(Hyin, k);
+            nCa = ldg(Cap, k);
+            nCs = ldg(Csp, k);
             const int ry = yrow(r, NY, npml);
             if (ry >= 0) {
-                const State &in = cold->fs[a.cur];
-                const size_t q = (size_t)s * a.ys + (size_t)ry * P + i;
-                nPs.x = in.phx[q];
-                nPs.w = in.pey[q];
+                const unsigned q = (unsigned)(ry * P + i);
+                nPs.x = ldg(cold->fs[a.cur].phx + (size_t)s * a.ys, q);
+                nPs.w = ldg(cold->fs[a.cur].pey + (size_t)s * a.ys, q);
             }
             if (xp) {
-                const State &in = cold->fs[a.cur];
-                const size_t q = (size_t)s * a.xs + (size_t)r * a.W + cx;
-                nPs.y = in.phy[q];
-                nPs.z = in.pex[q];
+                const unsigned q = (unsigned)(r * a.W + cx);
+                nPs.y = ldg(cold->fs[a.cur].phy + (size_t)s * a.xs, q);
+                nPs.z = ldg(cold->fs[a.cur].pex + (size_t)s * a.xs, q);
             }
         }
     };
@@ -248,17 +268,17 @@ __device__ __forceinline__ void fwd_body(const FwdStreamArgs &a, const WaveTile 
             const float hprev = (l + 1 < K) ? Hx_[p][l + 1] : hlast;
             const bool jown = j >= y0 && j < y1;
             if (a.record && jown && j >= rlo && j <= rhi) {    // stage 1
-                const StreamGeom &g = cold->g;
+                const int *rcol = cold->g.rcol, *ridx = cold->g.ridx;
                 int lo, hi;
-                rec_range(g, s, NY, a.R, j, w.x0, w.x0 + OW, lo, hi);
+                rec_range(cold->g.rrow, rcol, s, NY, a.R, j, w.x0, w.x0 + OW, lo, hi);
+                float *tr = cold->traces + ((size_t)s * a.nt + a.n + l) * a.R;
                 for (int q2 = lo; q2 < hi; ++q2)
-                    if (own && g.rcol[(size_t)s * a.R + q2] == i)
-                        cold->traces[((size_t)s * a.nt + a.n + l) * a.R +
-                                     g.ridx[(size_t)s * a.R + q2]] = pE;
+                    if (own && ldc(rcol, s * a.R + q2) == i)
+                        stg(tr, (unsigned)ldc(ridx, s * a.R + q2), pE);
             }
             const int ry = yrow(j, NY, npml);
             const bool yp = ry >= 0;
-            const RowPml rp = yp ? row_pml(cold->p, j, ch, rdy) : r0;
+            const RowPml rp = yp ? row_pml(cold, j, ch, rdy) : r0;
             // stages 2-3: H to n+l+1/2
             const float dEy = E_[q][l] - pE;
             const float dEx = from_right(pE) - pE;
@@ -288,7 +308,7 @@ __device__ __forceinline__ void fwd_body(const FwdStreamArgs &a, const WaveTile 
             }
             float e = pCa * pE + pCs * curl;
             if (j == sj && i == si)
-                e -= pCs * cold->g.wavelet[(size_t)s * a.nt + a.n + l] * a.src_scale;
+                e -= pCs * ldc(cold->g.wavelet + (size_t)s * a.nt, a.n + l) * a.src_scale;
             if (l + 1 < K) {
                 E_[q][l + 1] = e; Hx_[q][l + 1] = hx; Hy_[q][l + 1] = hy;
                 Ca_[q][l + 1] = pCa; Cs_[q][l + 1] = pCs;
@@ -297,24 +317,21 @@ __device__ __forceinline__ void fwd_body(const FwdStreamArgs &a, const WaveTile 
                 hlast = hx;
             }
             if (jown && own) {
-                const size_t k = (size_t)j * P + i;
-                if (a.E_lev) a.E_lev[(size_t)l * a.lev_stride + so + k] = e;
+                const unsigned k = (unsigned)(j * P + i);
+                if (a.E_lev) stg(a.E_lev + (size_t)l * a.lev_stride + so, k, e);
                 if (last) {
-                    if (!a.E_lev) a.E_out[so + k] = e;
-                    a.Hx_out[so + k] = hx;
-                    a.Hy_out[so + k] = hy;
-                    if (yp || xp) {
-                        const State &out = cold->fs[a.cur ^ 1];
-                        if (yp) {
-                            const size_t q2 = (size_t)s * a.ys + (size_t)ry * P + i;
-                            out.phx[q2] = ps.x;
-                            out.pey[q2] = ps.w;
-                        }
-                        if (xp) {
-                            const size_t q2 = (size_t)s * a.xs + (size_t)j * a.W + cx;
-                            out.phy[q2] = ps.y;
-                            out.pex[q2] = ps.z;
-                        }
+                    if (!a.E_lev) stg(a.E_out + so, k, e);
+                    stg(a.Hx_out + so, k, hx);
+                    stg(a.Hy_out + so, k, hy);
+                    if (yp) {
+                        const unsigned q2 = (unsigned)(ry * P + i);
+                        stg(cold->fs[a.cur ^ 1].phx + (size_t)s * a.ys, q2, ps.x);
+                        stg(cold->fs[a.cur ^ 1].pey + (size_t)s * a.ys, q2, ps.w);
+                    }
+                    if (xp) {
+                        const unsigned q2 = (unsigned)(j * a.W + cx);
+                        stg(cold->fs[a.cur ^ 1].phy + (size_t)s * a.xs, q2, ps.y);
+                        stg(cold->fs[a.cur ^ 1].pex + (size_t)s * a.xs, q2, ps.z);
                     }
                 }
             }
@@ -365,7 +382,7 @@ __global__ __launch_bounds__(64) void k_fwd(FwdStreamArgs a) {
 template <int K, bool EDGE, bool TAIL>
 __device__ __forceinline__ void adj_body(const AdjStreamArgs &a, const WaveTile &w,
                                          float4 (*ring)[64], float2 (*img)[64]) {
-    const StreamCold *__restrict__ cold = a.cold;
+    ColdRef cold = (ColdRef)a.cold;
     const int lane = threadIdx.x;
     const int s = w.s, i = w.i, y0 = w.y0, y1 = w.y1;
     const int NY = a.NY, P = a.pitch, npml = a.npml;
@@ -377,26 +394,26 @@ __device__ __forceinline__ void adj_body(const AdjStreamArgs &a, const WaveTile 
     const float ch = a.ch, rdx = a.rdx, rdy = a.rdy;
     ColPml c;
     if (EDGE) {
-        c = col_pml(cold->p, i, inx, ch, rdx);
+        c = col_pml(cold, i, inx, ch, rdx);
     } else {
         c = ColPml{ch * rdx, rdx, 0.f, 0.f, 0.f, 0.f};
     }
     const RowPml r0{ch * rdy, rdy, 0.f, 0.f, 0.f, 0.f};
-    const int si = cold->g.src_ij[2 * s], sj = cold->g.src_ij[2 * s + 1];
-    const int rlo = cold->g.rspan[2 * s], rhi = cold->g.rspan[2 * s + 1];
+    const int si = ldc<int>(cold->g.src_ij, 2 * s), sj = ldc<int>(cold->g.src_ij, 2 * s + 1);
+    const int rlo = ldc<int>(cold->g.rspan, 2 * s), rhi = ldc<int>(cold->g.rspan, 2 * s + 1);
     const size_t so = (size_t)s * a.plane;
-    const float *__restrict__ Lin = a.L_in + so;
-    const float *__restrict__ LHxin = a.LHx_in + so;
-    const float *__restrict__ LHyin = a.LHy_in + so;
-    const float *__restrict__ Cap = a.Ca;
-    const float *__restrict__ Csp = a.Cs;
-    const float *__restrict__ Ef = a.E_lev + so + (inx ? i : 0);
+    const float *Lin = a.L_in + so;
+    const float *LHxin = a.LHx_in + so;
+    const float *LHyin = a.LHy_in + so;
+    const float *Cap = a.Ca;
+    const float *Csp = a.Cs;
     const int rlast = min(NY - 1, y1 + nlev - 1);
 
     // forward Ez^{n_l}(j) of level l (n_l = n_top - 1 - l), 0 off the grid
     auto loadE = [&](int l, int j) {
         return (j >= 0 && j < NY && inx)
-                   ? Ef[(size_t)(a.n_top - 1 - l - a.n_base) * a.lev_stride + (size_t)j * P]
+                   ? ldg(a.E_lev + (size_t)(a.n_top - 1 - l - a.n_base) * a.lev_stride + so,
+                         (unsigned)(j * P + i))
                    : 0.f;
     };
 
@@ -417,24 +434,22 @@ __device__ __forceinline__ void adj_body(const AdjStreamArgs &a, const WaveTile 
         nL = nCa = nCs = nHx = nHy = 0.f;
         nPh = make_float4(0.f, 0.f, 0.f, 0.f);
         if (r >= 0 && r <= rlast && inx) {
-            const size_t k = (size_t)r * P + i;
-            nL = Lin[k];
-            nHx = LHxin[k];
-            nHy = LHyin[k];
-            nCa = Cap[k];
-            nCs = Csp[k];
+            const unsigned k = (unsigned)(r * P + i);
+            nL = ldg(Lin, k);
+            nHx = ldg(LHxin, k);
+            nHy = ldg(LHyin, k);
+            nCa = ldg(Cap, k);
+            nCs = ldg(Csp, k);
             const int ry = yrow(r, NY, npml);
             if (ry >= 0) {
-                const State &in = cold->as[a.cur];
-                const size_t q = (size_t)s * a.ys + (size_t)ry * P + i;
-                nPh.y = in.pey[q];
-                nPh.z = in.phx[q];
+                const unsigned q = (unsigned)(ry * P + i);
+                nPh.y = ldg(cold->as[a.cur].pey + (size_t)s * a.ys, q);
+                nPh.z = ldg(cold->as[a.cur].phx + (size_t)s * a.ys, q);
             }
             if (xp) {
-                const State &in = cold->as[a.cur];
-                const size_t q = (size_t)s * a.xs + (size_t)r * a.W + cx;
-                nPh.x = in.pex[q];
-                nPh.w = in.phy[q];
+                const unsigned q = (unsigned)(r * a.W + cx);
+                nPh.x = ldg(cold->as[a.cur].pex + (size_t)s * a.xs, q);
+                nPh.w = ldg(cold->as[a.cur].phy + (size_t)s * a.xs, q);
             }
         }
     };
@@ -457,11 +472,11 @@ __device__ __forceinline__ void adj_body(const AdjStreamArgs &a, const WaveTile 
             const float pL = L_[p][l], pCa = Ca_[p][l], pCs = Cs_[p][l];
             const bool jown = j >= y0 && j < y1;
             if (jown && j == sj && cold->src_adjoint && own && i == si)
-                cold->src_adjoint[(size_t)s * a.nt + n] = -pCs * pL * a.src_scale;
+                stg(cold->src_adjoint + (size_t)s * a.nt, (unsigned)n, -pCs * pL * a.src_scale);
             const int ry = yrow(j, NY, npml), ry1 = yrow(j + 1, NY, npml);
             const bool yp = ry >= 0, yp1 = ry1 >= 0;
-            const RowPml rp = yp ? row_pml(cold->p, j, ch, rdy) : r0;
-            const RowPml rp1 = yp1 ? row_pml(cold->p, j + 1, ch, rdy) : r0;
+            const RowPml rp = yp ? row_pml(cold, j, ch, rdy) : r0;
+            const RowPml rp1 = yp1 ? row_pml(cold, j + 1, ch, rdy) : r0;
             float4 ph = make_float4(0.f, 0.f, 0.f, 0.f);
             if (yp || xp) ph = l == 0 ? ph0[p] : ring[j & (K - 1)][lane];
             // A1: transposed E step, row j and the LDy of row j+1
@@ -490,12 +505,12 @@ __device__ __forceinline__ void adj_body(const AdjStreamArgs &a, const WaveTile 
             ldey_prev[l] = ldey;
             // A3: adjoint source of step n
             if (j >= rlo && j <= rhi) {
-                const StreamGeom &g2 = cold->g;
+                const int *rcol = cold->g.rcol, *ridx = cold->g.ridx;
                 int lo, hi;
-                rec_range(g2, s, NY, a.R, j, w.x0 - K, w.x0 - K + 64, lo, hi);
+                rec_range(cold->g.rrow, rcol, s, NY, a.R, j, w.x0 - K, w.x0 - K + 64, lo, hi);
                 const float *res = cold->residual + ((size_t)s * a.nt + n) * a.R;
                 for (int q2 = lo; q2 < hi; ++q2)
-                    if (g2.rcol[(size_t)s * a.R + q2] == i) le += res[g2.ridx[(size_t)s * a.R + q2]];
+                    if (ldc(rcol, s * a.R + q2) == i) le += ldc(res, ldc(ridx, s * a.R + q2));
             }
             // imaging
             float2 acc = l == 0 ? make_float2(0.f, 0.f) : img[j & (K - 1)][lane];
@@ -510,24 +525,21 @@ __device__ __forceinline__ void adj_body(const AdjStreamArgs &a, const WaveTile 
                 }
             }
             if (last && jown && own) {
-                const size_t k = (size_t)j * P + i;
-                a.L_out[so + k] = le;
-                a.LHx_out[so + k] = lhx;
-                a.LHy_out[so + k] = lhy;
-                a.S1[so + k] += acc.x;
-                a.S2[so + k] += acc.y;
-                if (yp || xp) {
-                    const State &out = cold->as[a.cur ^ 1];
-                    if (yp) {
-                        const size_t q2 = (size_t)s * a.ys + (size_t)ry * P + i;
-                        out.pey[q2] = ph.y;
-                        out.phx[q2] = ph.z;
-                    }
-                    if (xp) {
-                        const size_t q2 = (size_t)s * a.xs + (size_t)j * a.W + cx;
-                        out.pex[q2] = ph.x;
-                        out.phy[q2] = ph.w;
-                    }
+                const unsigned k = (unsigned)(j * P + i);
+                stg(a.L_out + so, k, le);
+                stg(a.LHx_out + so, k, lhx);
+                stg(a.LHy_out + so, k, lhy);
+                stg(a.S1 + so, k, ldg(a.S1 + so, k) + acc.x);
+                stg(a.S2 + so, k, ldg(a.S2 + so, k) + acc.y);
+                if (yp) {
+                    const unsigned q2 = (unsigned)(ry * P + i);
+                    stg(cold->as[a.cur ^ 1].pey + (size_t)s * a.ys, q2, ph.y);
+                    stg(cold->as[a.cur ^ 1].phx + (size_t)s * a.ys, q2, ph.z);
+                }
+                if (xp) {
+                    const unsigned q2 = (unsigned)(j * a.W + cx);
+                    stg(cold->as[a.cur ^ 1].pex + (size_t)s * a.xs, q2, ph.x);
+                    stg(cold->as[a.cur ^ 1].phy + (size_t)s * a.xs, q2, ph.w);
                 }
             }
         }

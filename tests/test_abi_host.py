@@ -121,6 +121,30 @@ def test_grid_parameter_checks(field, value):
     assert _status_forward(grid, geom) == fwi.FWI_EINVAL
 
 
+def test_grid_size_limits():
+    """Total grid sides 3 .. 2^20 and one shot's plane below 2^30 cells."""
+    fake = fwi.Geometry(np.array([[5, 5]]), np.array([[[6, 6]]]), FAKE)
+    dt = 1e-12
+    # NX = 16384 (pitch 16384), NY = 65536: exactly 2^30 cells is rejected
+    g = fwi.make_grid(16384, 65536, 0, 1, 0.01, 0.01, dt)
+    assert _status_forward(g, fake) == fwi.FWI_EINVAL
+    # one row fewer fits
+    g = fwi.make_grid(16384, 65535, 0, 1, 0.01, 0.01, dt)
+    out = ctypes.c_size_t()
+    assert fwi.lib().fwi_workspace_bytes(ctypes.byref(g), ctypes.byref(fake.c), 0,
+                                         ctypes.byref(out)) == fwi.FWI_OK
+    # NX = 16321 rounds up to the same pitch
+    g = fwi.make_grid(16321, 65536, 0, 1, 0.01, 0.01, dt)
+    assert _status_forward(g, fake) == fwi.FWI_EINVAL
+    g = fwi.make_grid(1 << 20, 8, 0, 1, 0.01, 0.01, dt)
+    assert fwi.lib().fwi_workspace_bytes(ctypes.byref(g), ctypes.byref(fake.c), 0,
+                                         ctypes.byref(out)) == fwi.FWI_OK
+    g = fwi.make_grid((1 << 20) + 1, 8, 0, 1, 0.01, 0.01, dt)
+    assert _status_forward(g, fake) == fwi.FWI_EINVAL
+    g = fwi.make_grid(2, 3, 0, 1, 0.01, 0.01, dt)
+    assert _status_forward(g, fake) == fwi.FWI_EINVAL
+
+
 def test_geometry_checks():
     cfg, grid, geom = _tiny()
     p = cfg.npml
