@@ -23,6 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 from paper_2506_20513_amd import inputs as I  # noqa: E402
+from paper_2506_20513_amd import rocprof_summary  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, AMD public specification
 
@@ -184,6 +185,12 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
     by = kernels[dom]["bytes_per_launch"]
     achieved = kernels[dom]["algorithmic_GBps"]
+    # measured HBM bytes per launch, from the committed counter summary of
+    # these same kernel sources and workload (None otherwise)
+    traffic = rocprof_summary.read_traffic(
+        os.path.join(ROOT, "profiles", f"k_fwd_k_adj_{args.workload}_counters.md"), dom,
+        [cfg.NX, cfg.NY], S)
+    measured = traffic / (kernels[dom]["avg_ms"] / 1e3) / 1e9 if traffic else None
     # algorithmic bytes of the whole step (forward + adjoint, one pass each)
     alg_step = cells * nt * (S * (24.0 + 28.0) + 16.0)
     out = {
@@ -209,8 +216,10 @@ def main():
         "effective_hbm_frac": round(alg_step / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None,
-                     "bytes_per_launch": by},
+                     "traffic": traffic, "traffic_unit": "bytes/launch",
+                     "bytes_per_launch": by,
+                     "measured_GBps": round(measured, 1) if measured else None,
+                     "measured_frac": round(measured / HBM_PEAK_GBS, 4) if measured else None},
         "kernels": kernels,
         "misfit": float(mis.item()),
     }
