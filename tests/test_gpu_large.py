@@ -1,0 +1,165 @@
+"""Parity at the full size of the benchmark workload: 2048 x 1024 interior
+cells plus a 20-cell CPML (2088 x 1064), 64 shots of 256 receivers, 6000
+steps, in the launch configuration the benchmark times (fwi_gradient_timed,
+all shots batched in one sweep, checkpointed adjoint).
+
+The oracle cannot afford all of it, so the checks are:
+  - traces of sampled shots (first and last) against the oracle run shot by
+    shot at the full length;
+  - the misfit against its definition evaluated from the returned traces;
+  - the gradient's additivity over shots (all shots = first half + second
+    half, each run as its own batch), and the untimed entry point matching
+    the timed one bit for bit;
+  - the gradient of one shot on the full grid, at a reduced number of steps,
+    against the oracle;
+  - the FP32 dot-product test <A w, r> = <w, A^T r> on the full grid.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_20513_amd import fwi
+from paper_2506_20513_amd import inputs as I
+from tests.gpu_util import Run, mask_near, np_, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TR_TOL = 1e-4
+GR_TOL = 1e-3
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    fwi.lib()
+
+
+def oracle_problem(cfg, eps, sig):
+    return oracle.Problem(eps, sig, cfg.npml, cfg.dx, cfg.dy, cfg.dt,
+                          cpml_order=cfg.cpml_order, cpml_sigma_scale=cfg.cpml_sigma_scale,
+                          cpml_kappa_max=cfg.cpml_kappa_max, cpml_alpha_max=cfg.cpml_alpha_max)
+
+
+@pytest.fixture(scope="module")
+def large():
+    import torch
+    cfg = I.config_large()
+    e, s, e0, s0 = I.model_for(cfg)
+    src, rec = I.geometry(cfg)
+    w = I.wavelets(cfg)
+    grid = fwi.grid_from_config(cfg)
+    print(f"large: {cfg.name} {cfg.NX}x{cfg.NY} nt={cfg.nt} shots={cfg.nshots}", flush=True)
+    obs, _ = Run(grid, src, rec, w, e, s).forward()
+    torch.cuda.synchronize()
+    print("large: observed data done", flush=True)
+    run = Run(grid, src, rec, w, e0, s0)
+    ws = run.workspace(fwi.GRADIENT_WORKSPACE)
+    mis = torch.full((1,), float("nan"), dtype=torch.float64, device=run.dev)
+    ge = torch.full((run.NY, run.NX), float("nan"), device=run.dev)
+    gs = torch.full((run.NY, run.NX), float("nan"), device=run.dev)
+    tr = torch.full((run.S, run.nt, run.R), float("nan"), device=run.dev)
+    tm = fwi.fwi_timing(sample_every=8)
+    fwi.fwi_gradient_timed(grid, run.geom, run.eps, run.sig, obs, mis, ge, gs, tr, ws, tm)
+    torch.cuda.synchronize()
+    print("large: timed gradient done", flush=True)
+    return dict(cfg=cfg, grid=grid, e0=e0, s0=s0, src=src, rec=rec, w=w, obs=obs, ws=ws,
+                mis=float(mis.item()), ge=np_(ge), gs=np_(gs), tr=np_(tr))
+
+
+def test_large_sampled_shot_traces(large):
+    cfg = large["cfg"]
+    P = oracle_problem(cfg, large["e0"], large["s0"])
+    for k in (0, cfg.nshots - 1):
+        print(f"large: oracle forward of shot {k}", flush=True)
+        otr, _ = P.forward(large["src"][k:k + 1], large["rec"][k:k + 1], large["w"][k:k + 1],
+                           cfg.nt)
+        err = rel_l2(large["tr"][k], otr[0])
+        print("shot", k, "traces rel L2", err, flush=True)
+        assert err <= TR_TOL
+
+
+def test_large_misfit_definition(large):
+    r = large["tr"].astype(np.float64) - np_(large["obs"]).astype(np.float64)
+    J = 0.5 * float(np.sum(r * r))
+    print("misfit", large["mis"], "from traces", J, flush=True)
+    assert np.isfinite(large["mis"]) and J > 0
+    assert abs(large["mis"] - J) <= 1e-9 * J
+
+
+def test_large_gradient_additive_over_shots(large):
+    """The batched gradient is the sum of the per-shot gradients: running the
+    two halves of the shots as separate batches (untimed entry point) and
+    adding them reproduces it up to one FP32 rounding per cell."""
+    cfg, h = large["cfg"], large["cfg"].nshots // 2
+    parts = []
+    for sl in (slice(0, h), slice(h, cfg.nshots)):
+        print(f"large: gradient of shots {sl.start}..{sl.stop - 1}", flush=True)
+        run = Run(large["grid"], large["src"][sl], large["rec"][sl], large["w"][sl],
+                  large["e0"], large["s0"])
+        mis, ge, gs, _ = run.gradient(large["obs"][sl].contiguous(), want_traces=False)
+        parts.append((float(mis.item()), np_(ge).astype(np.float64), np_(gs).astype(np.float64)))
+    ge_sum = parts[0][1] + parts[1][1]
+    gs_sum = parts[0][2] + parts[1][2]
+    e1, e2 = rel_l2(ge_sum, large["ge"]), rel_l2(gs_sum, large["gs"])
+    print("additivity rel L2", e1, e2, flush=True)
+    assert e1 <= 1e-5 and e2 <= 1e-5
+    assert abs(parts[0][0] + parts[1][0] - large["mis"]) <= 1e-9 * large["mis"]
+
+
+def test_large_untimed_entry_point_bitwise(large):
+    """fwi_gradient and fwi_gradient_timed launch the same work."""
+    import torch
+    run = Run(large["grid"], large["src"], large["rec"], large["w"], large["e0"], large["s0"])
+    print("large: untimed gradient", flush=True)
+    mis, ge, gs, tr = run.gradient(large["obs"], ws=large["ws"])
+    torch.cuda.synchronize()
+    assert float(mis.item()) == large["mis"]
+    assert np.array_equal(np_(ge), large["ge"]) and np.array_equal(np_(gs), large["gs"])
+    assert np.array_equal(np_(tr), large["tr"])
+
+
+def test_large_grid_single_shot_gradient_reduced_steps():
+    """Shot 0 on the full 2088 x 1064 grid, 600 steps: every strip and band of
+    the decomposition runs; gradient against the oracle.  In 600 steps the
+    wave has not reached the deeper anomalies, so the data of the true and
+    initial models nearly cancel; half the true-model data keeps the residual
+    well conditioned."""
+    cfg = I.config_large().with_(nt=600, nshots=1)
+    e, s, e0, s0 = I.model_for(cfg)
+    src, rec = I.geometry(cfg)
+    w = I.wavelets(cfg)
+    print("large-600: oracle observed data and gradient", flush=True)
+    obs, _ = oracle_problem(cfg, e, s).forward(src, rec, w, cfg.nt)
+    obs = (0.5 * obs).astype(np.float32)
+    J, oge, ogs, otr = oracle_problem(cfg, e0, s0).gradient(src, rec, w, obs, cfg.nt)
+    print("large-600: GPU gradient", flush=True)
+    mis, ge, gs, tr = Run(fwi.grid_from_config(cfg), src, rec, w, e0, s0).gradient(obs)
+    assert rel_l2(np_(tr), otr) <= TR_TOL
+    assert abs(float(mis.item()) - J) <= 1e-4 * J
+    m = mask_near(oge.shape, src, rec)
+    errs = dict(eps=rel_l2(np_(ge), oge), sig=rel_l2(np_(gs), ogs),
+                eps_masked=rel_l2(np_(ge)[m], oge[m]), sig_masked=rel_l2(np_(gs)[m], ogs[m]))
+    print("gradient rel L2:", errs, flush=True)
+    for k, v in errs.items():
+        assert v <= GR_TOL, (k, v)
+
+
+def test_large_grid_dot_product_fp32():
+    """<A w, r> = <w, A^T r> for the wavelet-to-trace map on the full grid
+    (two shots, 300 steps, history mode)."""
+    cfg = I.config_large().with_(nt=300, nshots=2)
+    e, s, _, _ = I.model_for(cfg)
+    src, rec = I.geometry(cfg)
+    rng = np.random.default_rng(11)
+    w = rng.standard_normal((2, cfg.nt)).astype(np.float32)
+    r = rng.standard_normal((2, cfg.nt, cfg.nrec)).astype(np.float32)
+    run = Run(fwi.grid_from_config(cfg), src, rec, w, e, s)
+    print("large-300: forward + adjoint", flush=True)
+    tr, ws = run.forward(fwi.FWI_SAVE_HISTORY)
+    _, _, sa = run.adjoint(r, fwi.FWI_SAVE_HISTORY, ws, want_src_adjoint=True)
+    lhs = float(np.sum(np_(tr).astype(np.float64) * r))
+    rhs = float(np.sum(w.astype(np.float64) * np_(sa)))
+    print("dot product", lhs, rhs, flush=True)
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
