@@ -1,0 +1,126 @@
+"""The autograd layer and the FWI driver on the GPU.
+
+- traces() with a loss of 1/2 sum (traces - observed)^2 back-propagates to
+  the same gradient the fused fwi_gradient call returns;
+- misfit() scales its stored gradient by the incoming gradient;
+- a backward pass after the problem ran another forward raises;
+- a short multiscale L-BFGS inversion on the 128x128 workload lowers the
+  misfit of every band and moves eps_r towards the true model.
+"""
+import numpy as np
+import pytest
+
+from paper_2506_20513_amd import fwi
+from paper_2506_20513_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    fwi.lib()
+
+
+@pytest.fixture(scope="module")
+def case():
+    import torch
+    from paper_2506_20513_amd import autograd as AG
+    cfg = I.config_tiny().with_(nt=600)
+    e, s, e0, s0 = I.model_for(cfg)
+    src, rec = I.geometry(cfg)
+    w = torch.from_numpy(I.wavelets(cfg)).cuda()
+    prob = AG.Problem(fwi.grid_from_config(cfg), src, rec, w)
+    T = lambda a: torch.from_numpy(a).cuda()
+    with torch.no_grad():
+        obs = AG.traces(prob, T(e), T(s))
+    return dict(cfg=cfg, prob=prob, e=T(e), s=T(s), e0=T(e0), s0=T(s0), w=w, obs=obs)
+
+
+def test_traces_backward_matches_fused_gradient(case):
+    import torch
+    from paper_2506_20513_amd import autograd as AG
+    prob = case["prob"]
+    e = case["e0"].clone().requires_grad_(True)
+    s = case["s0"].clone().requires_grad_(True)
+    tr = AG.traces(prob, e, s)
+    loss = 0.5 * ((tr - case["obs"]) ** 2).sum()
+    loss.backward()
+    ws = fwi.alloc_workspace(fwi.workspace_bytes(prob.grid, prob.geom, fwi.GRADIENT_WORKSPACE))
+    mis = torch.empty(1, dtype=torch.float64, device="cuda")
+    ge = torch.empty_like(e)
+    gs = torch.empty_like(s)
+    fwi.fwi_gradient(prob.grid, prob.geom, case["e0"], case["s0"], case["obs"], mis, ge, gs,
+                     None, ws)
+    torch.cuda.synchronize()
+    for a, b in ((e.grad, ge), (s.grad, gs)):
+        err = float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+        print("traces-backward vs fused gradient", err, flush=True)
+        assert err <= 1e-6
+    assert abs(float(loss) - float(mis)) <= 1e-5 * float(mis)
+
+
+def test_misfit_backward_scales_with_the_incoming_gradient(case):
+    from paper_2506_20513_amd import autograd as AG
+    prob = case["prob"]
+    e = case["e0"].clone().requires_grad_(True)
+    s = case["s0"].clone().requires_grad_(True)
+    J = AG.misfit(prob, e, s, case["obs"])
+    (3.0 * J).backward()
+    g3e, g3s = e.grad.clone(), s.grad.clone()
+    e.grad = None
+    s.grad = None
+    AG.misfit(prob, e, s, case["obs"]).backward()
+    assert J.dtype.is_floating_point and float(J) > 0
+    assert np.allclose(g3e.cpu().numpy(), 3.0 * e.grad.cpu().numpy(), rtol=1e-6, atol=0)
+    assert np.allclose(g3s.cpu().numpy(), 3.0 * s.grad.cpu().numpy(), rtol=1e-6, atol=0)
+
+
+def test_backward_after_another_forward_raises(case):
+    import torch
+    from paper_2506_20513_amd import autograd as AG
+    prob = case["prob"]
+    e = case["e0"].clone().requires_grad_(True)
+    tr1 = AG.traces(prob, e, case["s0"])
+    tr2 = AG.traces(prob, e, case["s0"])
+    with pytest.raises(RuntimeError):
+        tr1.sum().backward()
+    tr2.sum().backward()            # the latest one is still valid
+    torch.cuda.synchronize()
+    assert torch.isfinite(e.grad).all()
+
+
+def test_wrong_shapes_are_rejected_before_launch(case):
+    import torch
+    from paper_2506_20513_amd import autograd as AG
+    prob = case["prob"]
+    with pytest.raises(ValueError):
+        AG.traces(prob, case["e0"][:-1], case["s0"][:-1])
+    with pytest.raises(ValueError):
+        AG.misfit(prob, case["e0"], case["s0"], case["obs"][:, :-1])
+    with pytest.raises(TypeError):
+        AG.traces(prob, case["e0"].double(), case["s0"])
+
+
+def test_short_multiscale_inversion_reduces_misfit(case):
+    import torch
+    from paper_2506_20513_amd import fwi_loop as L
+    cfg, prob = case["cfg"], case["prob"]
+    st = L.Settings(bands=(100e6, None), iters=8, optimizer="lbfgs", tv_weight=1e-3)
+    r = L.invert(prob, case["w"], case["obs"], case["e0"], case["s0"], st, cfg.dt,
+                 log=lambda m: print(m, flush=True))
+    sl = (slice(cfg.npml, cfg.NY - cfg.npml), slice(cfg.npml, cfg.NX - cfg.npml))
+
+    def rel(a, b):
+        return float(torch.linalg.norm(a[sl] - b[sl]) / torch.linalg.norm(b[sl]))
+
+    for band in (100e6, 0.0):
+        h = [x for x in r.history if x.band == band]
+        print("band", band, "relative misfit", h[0].rel_misfit, "->", h[-1].rel_misfit, flush=True)
+        assert h[-1].rel_misfit < 0.7
+    e_before, e_after = rel(case["e0"], case["e"]), rel(r.eps_r, case["e"])
+    print("eps_r model error", e_before, "->", e_after, flush=True)
+    assert e_after < e_before
+    assert float(r.eps_r.min()) >= 1.0 and float(r.sigma.min()) >= 0.0
