@@ -76,8 +76,16 @@ class Problem:
         return (self.S, self.nt, self.R)
 
     def workspace(self, mode):
+        """The workspace for `mode`.  The checkpointing modes need tens to
+        hundreds of GB on large grids, so at most one of them is kept: taking
+        one frees the other (and invalidates saved checkpoints)."""
         ws = self._ws.get(mode)
         if ws is None:
+            if mode != fwi.FWI_SAVE_NONE:
+                for m in [m for m in self._ws if m != fwi.FWI_SAVE_NONE]:
+                    del self._ws[m]
+                self._generation += 1
+                torch.cuda.empty_cache()
             ws = fwi.alloc_workspace(fwi.workspace_bytes(self.grid, self.geom, mode), self.device)
             self._ws[mode] = ws
         return ws
@@ -97,9 +105,11 @@ class _Traces(torch.autograd.Function):
     def forward(ctx, eps_r, sigma, prob):
         _check_tensor("eps_r", eps_r, prob.model_shape)
         _check_tensor("sigma", sigma, prob.model_shape)
-        ws = prob.workspace(fwi.FWI_SAVE_CHECKPOINT)
+        # without a gradient to come, nothing needs saving for an adjoint
+        mode = fwi.FWI_SAVE_CHECKPOINT if any(ctx.needs_input_grad[:2]) else fwi.FWI_SAVE_NONE
+        ws = prob.workspace(mode)
         tr = torch.empty(prob.trace_shape, dtype=torch.float32, device=prob.device)
-        fwi.fdtd_forward(prob.grid, prob.geom, eps_r, sigma, tr, fwi.FWI_SAVE_CHECKPOINT, ws)
+        fwi.fdtd_forward(prob.grid, prob.geom, eps_r, sigma, tr, mode, ws)
         ctx.prob = prob
         ctx.generation = prob._next()
         ctx.save_for_backward(eps_r, sigma)
