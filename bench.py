@@ -75,12 +75,103 @@ def cpu_baseline(cfg, e0, s0, src, rec, w, steps: int):
                       f"(Ez history kept) + adjoint + gradient, FP64, {el:.1f} s"}
 
 
+def bench_uneven(args):
+    """Batched gradients of independent problems of uneven size (96 models,
+    interior grids 200x100 .. 640x320, 1500-4000 steps, 8 shots x 64
+    receivers): one plan, one graph replay per step."""
+    import torch
+    from paper_2506_20513_amd import fwi
+    cfgs = I.config_uneven(args.models)
+    dev = "cuda"
+    keep, probs = [], []
+    t0 = time.perf_counter()
+    for cfg in cfgs:
+        e, s, e0, s0 = I.model_for(cfg)
+        src, rec = I.geometry(cfg)
+        w = torch.from_numpy(I.wavelets(cfg)).to(dev)
+        grid = fwi.grid_from_config(cfg)
+        geom = fwi.Geometry(src, rec, w)
+        et, st_, e0t, s0t = (torch.from_numpy(a).to(dev) for a in (e, s, e0, s0))
+        obs = torch.empty((cfg.nshots, cfg.nt, cfg.nrec), device=dev)
+        wsf = fwi.alloc_workspace(fwi.workspace_bytes(grid, geom, fwi.FWI_SAVE_NONE), dev)
+        fwi.fdtd_forward(grid, geom, et, st_, obs, fwi.FWI_SAVE_NONE, wsf)
+        mis = torch.empty(1, dtype=torch.float64, device=dev)
+        ge = torch.empty((cfg.NY, cfg.NX), device=dev)
+        gs = torch.empty((cfg.NY, cfg.NX), device=dev)
+        probs.append(fwi.BatchProblem(grid, geom, e0t, s0t, obs, mis, ge, gs))
+        keep.append((w, wsf))
+    torch.cuda.synchronize()
+    keep = [k[0] for k in keep]
+    log(f"bench: {len(cfgs)} problems ready ({time.perf_counter() - t0:.1f} s)")
+    ws_bytes = fwi.batch_workspace_bytes(probs)
+    ws = fwi.alloc_workspace(ws_bytes, dev)
+    t0 = time.perf_counter()
+    plan = fwi.BatchPlan(probs, ws, autotune=not args.no_autotune)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    info = plan.info()
+    log(f"bench: plan in {plan_s:.1f} s, workspace {ws_bytes / 1e9:.1f} GB, {info}")
+    for k in range(args.warmup):
+        plan.run()
+        torch.cuda.synchronize()
+        log(f"bench: warmup {k + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        plan.run()
+        torch.cuda.synchronize()
+        log(f"bench: step {k + 1}/{args.steps} done")
+    el = time.perf_counter() - t0
+    ms_per_step = el / args.steps * 1e3
+    updates = sum(c.NX * c.NY * c.nt * c.nshots * 2 for c in cfgs)
+    interior = sum(c.nx * c.ny * c.nt * c.nshots * 2 for c in cfgs)
+    alg = sum(c.NX * c.NY * c.nt * (c.nshots * (24.0 + 28.0) + 16.0) for c in cfgs)
+    out = {
+        "metric": "Gcell-updates/s fwd+adjoint FDTD (eps_r/sigma gradient), batched uneven models",
+        "value": round(updates / (ms_per_step / 1e3) / 1e9, 3),
+        "unit": "Gcell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"uneven: {len(cfgs)} independent models, interior 200x100 .. "
+                               f"640x320 at dx=0.01 m, 1500-4000 steps, 8 shots x 64 receivers, "
+                               f"Ricker 200 MHz", "models": len(cfgs),
+                   "workspace_GB": round(ws_bytes / 1e9, 2)},
+        "interior_gcells": round(interior / (ms_per_step / 1e3) / 1e9, 3),
+        "effective_hbm_frac": round(alg / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "plan": info, "plan_seconds": round(plan_s, 2),
+    }
+    if args.sequential:
+        # the same problems one after another through fwi_gradient, in one
+        # workspace large enough for any of them
+        need = max(fwi.workspace_bytes(p.grid, p.geom, fwi.GRADIENT_WORKSPACE) for p in probs)
+        del ws
+        plan.close()
+        torch.cuda.empty_cache()
+        w1 = fwi.alloc_workspace(need, dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for p in probs:
+            a = p.arrays
+            fwi.fwi_gradient(p.grid, p.geom, a[0], a[1], a[2], a[3], a[4], a[5], None, w1)
+        torch.cuda.synchronize()
+        seq = time.perf_counter() - t0
+        out["sequential_ms"] = round(seq * 1e3, 1)
+        out["batched_speedup"] = round(seq * 1e3 / ms_per_step, 2)
+        log(f"bench: sequential single-problem calls {seq:.2f} s")
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS) + ["uneven"])
+    ap.add_argument("--models", type=int, default=96, help="uneven workload: number of models")
+    ap.add_argument("--no-autotune", action="store_true", help="uneven workload: default bands")
+    ap.add_argument("--sequential", action="store_true",
+                    help="uneven workload: also time the problems one by one")
     ap.add_argument("--sample-every", type=int, default=8,
                     help="time every k-th launch of each hot kernel with HIP events")
     ap.add_argument("--cpu-steps", type=int, default=2400)
@@ -105,6 +196,8 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     fwi.lib()
+    if args.workload == "uneven":
+        return bench_uneven(args)
 
     cfg = WORKLOADS[args.workload]()
     if args.nt is not None:

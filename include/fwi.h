@@ -199,6 +199,73 @@ int fwi_checkpoint_interval(const fwi_grid *grid, const fwi_geom *geom,
 /* Static text for a status code. */
 const char *fwi_strerror(int status);
 
+/* ---- Batched gradients of independent problems ----------------------------
+ * fwi_gradient for many independent problems at once (Secs. 2.1, 3.3): each
+ * problem has its own grid, model, geometry, wavelet, observed data and time
+ * length.  A plan records every problem's gradient evaluation, merges the
+ * stencil passes that fall on the same step of a common schedule (all
+ * problems share one checkpoint interval) into one launch, and captures the
+ * whole sequence in a HIP graph that each run replays.  For batches of
+ * models too small to fill the GPU one at a time.  Results equal those of
+ * fwi_gradient on each problem, bit for bit.
+ *
+ * Ownership: the plan is a host object made by fwi_batch_plan_create and
+ * released by fwi_batch_plan_destroy.  It keeps the device addresses of the
+ * caller's arrays and workspace, which must stay allocated while the plan
+ * is used; their contents (models, observed data) may change between runs.
+ * Host geometry tables are copied at creation.  Runs of one plan must be
+ * ordered on one stream. */
+typedef struct fwi_batch_problem {
+    fwi_grid grid;
+    fwi_geom geom;
+    const float *eps_r;        /* device [NY][NX]                             */
+    const float *sigma;        /* device [NY][NX]                             */
+    const float *observed;     /* device [nshots][nt][nrec]                   */
+    double *misfit;            /* device, one double, J = 1/2 sum r^2         */
+    float *grad_eps_r;         /* device [NY][NX], overwritten                */
+    float *grad_sigma;         /* device [NY][NX], overwritten                */
+} fwi_batch_problem;
+
+typedef struct fwi_batch_info {
+    int32_t nproblems;
+    int32_t checkpoint_interval; /* common to all problems                   */
+    int32_t band_rows;         /* row-band height in use (0: per-problem default) */
+    int32_t steps;             /* operations per run                          */
+    int32_t stencil_launches;  /* merged stencil launches per run             */
+    int32_t graph;             /* 1: runs replay a captured HIP graph         */
+    int32_t ntune;             /* band heights timed by the autotuner         */
+    int32_t tune_rows[8];      /* the heights (0: per-problem default)        */
+    double tune_ms[8];         /* first merged forward pass, best of 3, ms    */
+} fwi_batch_info;
+
+typedef struct fwi_batch_plan fwi_batch_plan;
+
+/* Workspace for a batch (host out `bytes`); statuses as fwi_workspace_bytes
+ * for the first invalid problem, FWI_EINVAL for nproblems < 1 or a null
+ * device pointer in a problem. */
+int fwi_batch_workspace_bytes(int32_t nproblems, const fwi_batch_problem *problems,
+                              size_t *bytes);
+
+/* Validate, lay out the workspace, upload geometry and schedule tables,
+ * optionally time candidate row-band heights (autotune != 0: runs stencil
+ * passes on the workspace), and capture the graph.  Synchronises `stream`.
+ * *plan receives the plan (NULL on error); FWI_ENOMEM if ws is missing,
+ * misaligned or smaller than fwi_batch_workspace_bytes. */
+int fwi_batch_plan_create(int32_t nproblems, const fwi_batch_problem *problems, void *ws,
+                          size_t ws_bytes, int32_t autotune, void *stream,
+                          fwi_batch_plan **plan);
+
+/* One gradient evaluation of every problem: misfit and gradients written to
+ * each problem's outputs.  use_graph = 0 issues the same operations one by
+ * one instead of replaying the graph (same results).  Asynchronous. */
+int fwi_batch_plan_run(fwi_batch_plan *plan, int32_t use_graph, void *stream);
+
+/* Plan statistics (host out `info`). */
+int fwi_batch_plan_info(const fwi_batch_plan *plan, fwi_batch_info *info);
+
+/* Release a plan (NULL is ignored).  The caller's arrays are untouched. */
+void fwi_batch_plan_destroy(fwi_batch_plan *plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -2,8 +2,7 @@
 // before any HIP call), workspace layout, and the time loops of the forward
 // sweep (Algorithm 1), the adjoint sweep (Algorithm 2) and the full gradient
 // evaluation.  Paper: arXiv 2506.20513, Secs. 2.1 and 3.3.
-#include "fwi.h"
-#include "fwi_internal.h"
+#include "fwi_host.h"
 
 #include <algorithm>
 #include <cmath>
@@ -12,9 +11,8 @@
 #include <vector>
 
 namespace fwi {
-namespace {
+namespace host {
 
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
@@ -123,7 +121,7 @@ void make_tiling(const Dims &d, Layout &L) {
 }
 
 // Workspace layout for a mode (FWI_SAVE_* or -1 = fwi_gradient).
-int make_layout(const Dims &d, int mode, Layout &L) {
+int make_layout(const Dims &d, int mode, Layout &L, int k) {
     if (mode != FWI_SAVE_NONE && mode != FWI_SAVE_CHECKPOINT &&
         mode != FWI_SAVE_HISTORY && mode != -1)
         return FWI_EINVAL;
@@ -160,7 +158,7 @@ int make_layout(const Dims &d, int mode, Layout &L) {
     } else if (mode == FWI_SAVE_HISTORY) {
         L.nslots = d.nt + 1;
     } else {
-        L.K = choose_k(d);
+        L.K = k > 0 ? std::min(k, d.nt) : choose_k(d);
         L.ncp = (d.nt + L.K - 1) / L.K;
         L.nslots = L.K + 1;
     }
@@ -188,118 +186,6 @@ int make_layout(const Dims &d, int mode, Layout &L) {
     make_tiling(d, L);
     return FWI_OK;
 }
-
-// Pointers into the workspace.
-struct Ptrs {
-    char *base;
-    const Layout *L;
-    float *f(size_t off) const { return reinterpret_cast<float *>(base + off); }
-    int *i(size_t off) const { return reinterpret_cast<int *>(base + off); }
-    Profiles prof() const {
-        const Dims &d = L->d;
-        float *p = f(L->off_prof);
-        Profiles q;
-        q.bEx = p; q.aEx = p + d.NX; q.kEx = p + 2 * d.NX;
-        q.bHx = p + 3 * d.NX; q.aHx = p + 4 * d.NX; q.kHx = p + 5 * d.NX;
-        float *y = p + 6 * d.NX;
-        q.bEy = y; q.aEy = y + d.NY; q.kEy = y + 2 * d.NY;
-        q.bHy = y + 3 * d.NY; q.aHy = y + 4 * d.NY; q.kHy = y + 5 * d.NY;
-        return q;
-    }
-    // A State laid out at `off`: [E][Hx][Hy][phx][phy][pex][pey] (E only when
-    // with_e).
-    State state(size_t off, bool with_e) const {
-        const Dims &d = L->d;
-        const size_t S = (size_t)d.S;
-        const size_t field = align_up(S * d.plane * sizeof(float));
-        const size_t xs = align_up(S * d.xs * sizeof(float));
-        const size_t ys = align_up(S * d.ys * sizeof(float));
-        State st;
-        size_t o = off;
-        st.E = nullptr;
-        if (with_e) { st.E = f(o); o += field; }
-        st.Hx = f(o); o += field;
-        st.Hy = f(o); o += field;
-        st.phx = f(o); o += ys;
-        st.phy = f(o); o += xs;
-        st.pex = f(o); o += xs;
-        st.pey = f(o);
-        return st;
-    }
-    float *slot(int k) const {
-        const Dims &d = L->d;
-        return f(L->off_slots) + (size_t)k * d.S * d.plane;
-    }
-};
-
-#define FWI_TRY(expr)                                   \
-    do {                                                \
-        hipError_t e_ = (expr);                         \
-        if (e_ != hipSuccess) return FWI_EHIP;          \
-    } while (0)
-
-// Optional per-kernel timing with HIP events on the call's stream.
-enum Kind { K_FWD = 0, K_ADJ = 1, K_NKINDS = 2 };
-const char *const kKindName[K_NKINDS] = {"k_fwd", "k_adj"};
-
-struct Timer {
-    fwi_timing *t = nullptr;
-    hipStream_t st = nullptr;
-    int launches[K_NKINDS] = {0, 0};
-    double updates[K_NKINDS] = {0, 0};
-    struct Rec { int kind; hipEvent_t a, b; };
-    std::vector<Rec> recs;
-    bool failed = false;
-
-    // Launch `fn` (returning hipError_t), bracketed by events when sampled.
-    template <class F>
-    hipError_t run(int kind, double cell_updates, F fn) {
-        updates[kind] += cell_updates;
-        const int idx = launches[kind]++;
-        if (!t || idx % t->sample_every != 0 || failed) return fn();
-        Rec r{kind, nullptr, nullptr};
-        if (hipEventCreate(&r.a) != hipSuccess) { failed = true; return fn(); }
-        if (hipEventCreate(&r.b) != hipSuccess) {
-            hipEventDestroy(r.a);
-            failed = true;
-            return fn();
-        }
-        hipError_t e = hipEventRecord(r.a, st);
-        if (e == hipSuccess) e = fn();
-        if (e == hipSuccess) e = hipEventRecord(r.b, st);
-        recs.push_back(r);
-        return e;
-    }
-
-    int finish() {
-        if (!t) return FWI_OK;
-        double sum[K_NKINDS] = {0, 0};
-        int cnt[K_NKINDS] = {0, 0};
-        int rc = FWI_OK;
-        if (hipStreamSynchronize(st) != hipSuccess) rc = FWI_EHIP;
-        for (auto &r : recs) {
-            float ms = 0.f;
-            if (rc == FWI_OK && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
-                sum[r.kind] += ms;
-                cnt[r.kind] += 1;
-            }
-            hipEventDestroy(r.a);
-            hipEventDestroy(r.b);
-        }
-        recs.clear();
-        t->nkinds = K_NKINDS;
-        for (int k = 0; k < K_NKINDS; ++k) {
-            fwi_kernel_time &o = t->kind[k];
-            std::memset(o.name, 0, sizeof(o.name));
-            std::strncpy(o.name, kKindName[k], sizeof(o.name) - 1);
-            o.launches = launches[k];
-            o.timed = cnt[k];
-            o.avg_ms = cnt[k] ? sum[k] / cnt[k] : 0.0;
-            o.cell_updates = updates[k];
-        }
-        return rc;
-    }
-};
 
 // Geometry to the device: sources, and per shot the receivers sorted by
 // (row, column) - stable in receiver index, so receivers sharing a cell stay
@@ -430,6 +316,100 @@ FwdStreamArgs fwd_args(const Ptrs &P) {
     return a;
 }
 
+AdjStreamArgs adj_args(const Ptrs &P) {
+    const Layout &L = *P.L;
+    const Dims &d = L.d;
+    AdjStreamArgs a;
+    a.NX = d.NX; a.NY = d.NY; a.npml = d.npml; a.pitch = d.pitch;
+    a.W = d.W; a.S = d.S; a.R = d.R; a.nt = d.nt;
+    a.n_top = a.n_base = a.nlev = a.cur = 0;
+    a.tl = tiling(P);
+    a.plane = d.plane; a.xs = d.xs; a.ys = d.ys;
+    a.lev_stride = (size_t)d.S * d.plane;
+    a.ch = (float)(d.dt / kMu0);
+    a.rdx = (float)(1.0 / d.dx);
+    a.rdy = (float)(1.0 / d.dy);
+    a.src_scale = (float)(1.0 / (d.dx * d.dy));
+    a.Ca = P.f(L.off_Ca);
+    a.Cs = P.f(L.off_Cs);
+    a.E_lev = nullptr;
+    a.L_in = a.LHx_in = a.LHy_in = nullptr;
+    a.L_out = a.LHx_out = a.LHy_out = nullptr;
+    a.S1 = L.off_S1 ? P.f(L.off_S1) : nullptr;
+    a.S2 = L.off_S2 ? P.f(L.off_S2) : nullptr;
+    a.cold = reinterpret_cast<const StreamCold *>(P.base + L.off_cold);
+    return a;
+}
+
+}  // namespace host
+
+namespace {
+
+using namespace host;
+
+// Optional per-kernel timing with HIP events on the call's stream.
+enum Kind { K_FWD = 0, K_ADJ = 1, K_NKINDS = 2 };
+const char *const kKindName[K_NKINDS] = {"k_fwd", "k_adj"};
+
+struct Timer {
+    fwi_timing *t = nullptr;
+    hipStream_t st = nullptr;
+    int launches[K_NKINDS] = {0, 0};
+    double updates[K_NKINDS] = {0, 0};
+    struct Rec { int kind; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+    bool failed = false;
+
+    // Launch `fn` (returning hipError_t), bracketed by events when sampled.
+    template <class F>
+    hipError_t run(int kind, double cell_updates, F fn) {
+        updates[kind] += cell_updates;
+        const int idx = launches[kind]++;
+        if (!t || idx % t->sample_every != 0 || failed) return fn();
+        Rec r{kind, nullptr, nullptr};
+        if (hipEventCreate(&r.a) != hipSuccess) { failed = true; return fn(); }
+        if (hipEventCreate(&r.b) != hipSuccess) {
+            (void)hipEventDestroy(r.a);
+            failed = true;
+            return fn();
+        }
+        hipError_t e = hipEventRecord(r.a, st);
+        if (e == hipSuccess) e = fn();
+        if (e == hipSuccess) e = hipEventRecord(r.b, st);
+        recs.push_back(r);
+        return e;
+    }
+
+    int finish() {
+        if (!t) return FWI_OK;
+        double sum[K_NKINDS] = {0, 0};
+        int cnt[K_NKINDS] = {0, 0};
+        int rc = FWI_OK;
+        if (hipStreamSynchronize(st) != hipSuccess) rc = FWI_EHIP;
+        for (auto &r : recs) {
+            float ms = 0.f;
+            if (rc == FWI_OK && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+                sum[r.kind] += ms;
+                cnt[r.kind] += 1;
+            }
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        recs.clear();
+        t->nkinds = K_NKINDS;
+        for (int k = 0; k < K_NKINDS; ++k) {
+            fwi_kernel_time &o = t->kind[k];
+            std::memset(o.name, 0, sizeof(o.name));
+            std::strncpy(o.name, kKindName[k], sizeof(o.name) - 1);
+            o.launches = launches[k];
+            o.timed = cnt[k];
+            o.avg_ms = cnt[k] ? sum[k] / cnt[k] : 0.0;
+            o.cell_updates = updates[k];
+        }
+        return rc;
+    }
+};
+
 // Coefficients, profiles, geometry and the cold arguments.
 int setup(const Ptrs &P, const fwi_geom *g, const StreamCold &cold, const float *eps_r,
           const float *sigma, hipStream_t st) {
@@ -529,27 +509,16 @@ int do_adjoint(const Layout &L, const float *eps_r, const float *sigma, float *g
     FWI_TRY(launch_fill(S1, field, 0.f, st));
     FWI_TRY(launch_fill(S2, field, 0.f, st));
 
-    AdjStreamArgs a;
-    a.NX = d.NX; a.NY = d.NY; a.npml = d.npml; a.pitch = d.pitch;
-    a.W = d.W; a.S = d.S; a.R = d.R; a.nt = d.nt;
-    a.tl = tiling(P);
-    a.plane = d.plane; a.xs = d.xs; a.ys = d.ys;
-    a.lev_stride = field;
-    a.ch = (float)(d.dt / kMu0);
-    a.rdx = (float)(1.0 / d.dx);
-    a.rdy = (float)(1.0 / d.dy);
-    a.src_scale = (float)(1.0 / (d.dx * d.dy));
-    a.Ca = P.f(L.off_Ca);
-    a.Cs = P.f(L.off_Cs);
-    a.S1 = S1;
-    a.S2 = S2;
-    a.cold = reinterpret_cast<const StreamCold *>(P.base + L.off_cold);
+    AdjStreamArgs a = adj_args(P);
     int acur = 0;
     const double all = (double)d.NX * d.NY * d.S;
-    // adjoint passes over steps [n_lo, n_hi), the forward Ez^{n_lo + k} in slot k
+    // adjoint passes over steps [n_lo, n_hi), the forward Ez^{n_lo + k} in slot k.
+    // Every pass starts at a multiple of the streaming depth (a partial pass
+    // first, at the top), so the grouping of the imaging sums, and with it
+    // every rounding, is the same for any checkpoint interval.
     auto adj_range = [&](int n_hi, int n_lo) -> int {
-        for (int n_top = n_hi; n_top > n_lo; n_top -= kStreamK) {
-            a.nlev = std::min(kStreamK, n_top - n_lo);
+        for (int n_top = n_hi; n_top > n_lo; n_top -= a.nlev) {
+            a.nlev = n_top - std::max(n_lo, (n_top - 1) / kStreamK * kStreamK);
             a.n_top = n_top;
             a.n_base = n_lo;
             a.E_lev = P.slot(0);
@@ -611,6 +580,7 @@ int prepare(const fwi_grid *grid, const fwi_geom *geom, int mode, void *ws,
 }  // namespace fwi
 
 using namespace fwi;
+using namespace fwi::host;
 
 extern "C" int fwi_workspace_bytes(const fwi_grid *grid, const fwi_geom *geom,
                                    int save_mode, size_t *bytes) {

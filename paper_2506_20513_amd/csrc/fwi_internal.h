@@ -163,5 +163,14 @@ hipError_t launch_residual_misfit(const float *traces, const float *observed,
 // streaming kernels (fwi_stream.hip)
 hipError_t launch_fwd_stream(const FwdStreamArgs &a, hipStream_t st);
 hipError_t launch_adj_stream(const AdjStreamArgs &a, hipStream_t st);
+// Blocks one problem's pass launches.
+unsigned stream_blocks(int S, const Tiling &tl);
+// One pass for nm problems at once: tab[m] (device) holds problem m's
+// arguments and boff[0..nm] (device) the prefix sums of their block counts,
+// nblocks = boff[nm].  tail: some problem advances fewer than kStreamK levels.
+hipError_t launch_fwd_table(const FwdStreamArgs *tab, const unsigned *boff, int nm,
+                            unsigned nblocks, bool tail, hipStream_t st);
+hipError_t launch_adj_table(const AdjStreamArgs *tab, const unsigned *boff, int nm,
+                            unsigned nblocks, bool tail, hipStream_t st);
 
 }  // namespace fwi

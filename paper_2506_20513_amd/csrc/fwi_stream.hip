@@ -155,10 +155,10 @@ struct WaveTile {
 // outside the grid; interior strips take the specialised path (kappa = 1,
 // no CPML memory, no bounds test).
 template <int K>
-__device__ __forceinline__ WaveTile wave_tile(const Tiling &tl, int S, int NX, int npml) {
+__device__ __forceinline__ WaveTile wave_tile(const Tiling &tl, int S, int NX, int npml,
+                                              int wid) {
     constexpr int OW = 64 - 2 * K;
     WaveTile w;
-    const int wid = xcd_logical(blockIdx.x, gridDim.x);
     w.s = wid % S;
     const int strip = (wid / S) % tl.nstrip;
     const int band = wid / (S * tl.nstrip);
@@ -348,7 +348,47 @@ template <int K, bool TAIL>
 __global__ __launch_bounds__(64) void k_fwd(FwdStreamArgs a) {
     static_assert((K & (K - 1)) == 0, "K must be a power of two");
     __shared__ float4 ring[K][64];
-    const WaveTile w = wave_tile<K>(a.tl, a.S, a.NX, a.npml);
+    const WaveTile w =
+        wave_tile<K>(a.tl, a.S, a.NX, a.npml, xcd_logical(blockIdx.x, gridDim.x));
+    if (w.edge)
+        fwd_body<K, true, TAIL>(a, w, ring);
+    else
+        fwd_body<K, false, TAIL>(a, w, ring);
+}
+
+// A struct read from the constant address space dword by dword (scalar
+// loads; unused fields are never loaded).
+template <class T>
+__device__ __forceinline__ T load_const(const T *p, int m) {
+    static_assert(sizeof(T) % 4 == 0, "dword-sized struct");
+    T v;
+    const FWI_AS_CONST unsigned *src = (const FWI_AS_CONST unsigned *)(p + m);
+    unsigned *dst = reinterpret_cast<unsigned *>(&v);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) dst[k] = src[k];
+    return v;
+}
+
+// The same pass for several independent problems in one launch: problem m
+// owns blocks [boff[m], boff[m+1]) of the XCD-renumbered block order and
+// reads its arguments from tab[m].
+__device__ __forceinline__ int table_entry(const unsigned *boff, int nm, unsigned lb) {
+    int lo = 0, hi = nm;                      // boff[lo] <= lb < boff[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (ldc(boff, mid) <= lb) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+template <int K, bool TAIL>
+__global__ __launch_bounds__(64) void k_fwd_tab(const FwdStreamArgs *tab, const unsigned *boff,
+                                                int nm) {
+    __shared__ float4 ring[K][64];
+    const unsigned lb = (unsigned)xcd_logical(blockIdx.x, gridDim.x);
+    const int m = table_entry(boff, nm, lb);
+    const FwdStreamArgs a = load_const(tab, m);
+    const WaveTile w = wave_tile<K>(a.tl, a.S, a.NX, a.npml, (int)(lb - ldc(boff, m)));
     if (w.edge)
         fwd_body<K, true, TAIL>(a, w, ring);
     else
@@ -556,7 +596,23 @@ __global__ __launch_bounds__(64) void k_adj(AdjStreamArgs a) {
     static_assert((K & (K - 1)) == 0, "K must be a power of two");
     __shared__ float4 ring[K][64];
     __shared__ float2 img[K][64];
-    const WaveTile w = wave_tile<K>(a.tl, a.S, a.NX, a.npml);
+    const WaveTile w =
+        wave_tile<K>(a.tl, a.S, a.NX, a.npml, xcd_logical(blockIdx.x, gridDim.x));
+    if (w.edge)
+        adj_body<K, true, TAIL>(a, w, ring, img);
+    else
+        adj_body<K, false, TAIL>(a, w, ring, img);
+}
+
+template <int K, bool TAIL>
+__global__ __launch_bounds__(64) void k_adj_tab(const AdjStreamArgs *tab, const unsigned *boff,
+                                                int nm) {
+    __shared__ float4 ring[K][64];
+    __shared__ float2 img[K][64];
+    const unsigned lb = (unsigned)xcd_logical(blockIdx.x, gridDim.x);
+    const int m = table_entry(boff, nm, lb);
+    const AdjStreamArgs a = load_const(tab, m);
+    const WaveTile w = wave_tile<K>(a.tl, a.S, a.NX, a.npml, (int)(lb - ldc(boff, m)));
     if (w.edge)
         adj_body<K, true, TAIL>(a, w, ring, img);
     else
@@ -564,6 +620,30 @@ __global__ __launch_bounds__(64) void k_adj(AdjStreamArgs a) {
 }
 
 }  // namespace
+
+unsigned stream_blocks(int S, const Tiling &tl) {
+    return (unsigned)S * tl.nstrip * tl.nband;
+}
+
+hipError_t launch_fwd_table(const FwdStreamArgs *tab, const unsigned *boff, int nm,
+                            unsigned nblocks, bool tail, hipStream_t st) {
+    if (nblocks == 0) return hipSuccess;
+    if (tail)
+        hipLaunchKernelGGL((k_fwd_tab<kStreamK, true>), dim3(nblocks), dim3(64), 0, st, tab, boff, nm);
+    else
+        hipLaunchKernelGGL((k_fwd_tab<kStreamK, false>), dim3(nblocks), dim3(64), 0, st, tab, boff, nm);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_table(const AdjStreamArgs *tab, const unsigned *boff, int nm,
+                            unsigned nblocks, bool tail, hipStream_t st) {
+    if (nblocks == 0) return hipSuccess;
+    if (tail)
+        hipLaunchKernelGGL((k_adj_tab<kStreamK, true>), dim3(nblocks), dim3(64), 0, st, tab, boff, nm);
+    else
+        hipLaunchKernelGGL((k_adj_tab<kStreamK, false>), dim3(nblocks), dim3(64), 0, st, tab, boff, nm);
+    return hipGetLastError();
+}
 
 hipError_t launch_fwd_stream(const FwdStreamArgs &a, hipStream_t st) {
     const unsigned nb = (unsigned)a.S * a.tl.nstrip * a.tl.nband;

@@ -30,7 +30,9 @@ FWI_SAVE_HISTORY = 2
 GRADIENT_WORKSPACE = -1   # fwi_workspace_bytes mode for fwi_gradient
 
 EXPORTED = ("fwi_workspace_bytes", "fdtd_forward", "fdtd_adjoint", "fwi_gradient",
-            "fwi_gradient_timed", "fwi_checkpoint_interval", "fwi_strerror")
+            "fwi_gradient_timed", "fwi_checkpoint_interval", "fwi_strerror",
+            "fwi_batch_workspace_bytes", "fwi_batch_plan_create", "fwi_batch_plan_run",
+            "fwi_batch_plan_info", "fwi_batch_plan_destroy")
 
 
 class FwiError(RuntimeError):
@@ -80,6 +82,27 @@ class fwi_geom(ctypes.Structure):
 _lib = None
 
 
+class fwi_batch_problem(ctypes.Structure):
+    _fields_ = [("grid", fwi_grid), ("geom", fwi_geom),
+                ("eps_r", ctypes.c_void_p), ("sigma", ctypes.c_void_p),
+                ("observed", ctypes.c_void_p), ("misfit", ctypes.c_void_p),
+                ("grad_eps_r", ctypes.c_void_p), ("grad_sigma", ctypes.c_void_p)]
+
+
+class fwi_batch_info(ctypes.Structure):
+    _fields_ = [("nproblems", ctypes.c_int32), ("checkpoint_interval", ctypes.c_int32),
+                ("band_rows", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("stencil_launches", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("ntune", ctypes.c_int32), ("tune_rows", ctypes.c_int32 * 8),
+                ("tune_ms", ctypes.c_double * 8)]
+
+    def as_dict(self):
+        return {"nproblems": self.nproblems, "checkpoint_interval": self.checkpoint_interval,
+                "band_rows": self.band_rows, "steps": self.steps,
+                "stencil_launches": self.stencil_launches, "graph": bool(self.graph),
+                "tuning": [(self.tune_rows[k], self.tune_ms[k]) for k in range(self.ntune)]}
+
+
 def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
@@ -98,8 +121,18 @@ def lib() -> ctypes.CDLL:
                                          ctypes.POINTER(fwi_timing)]
         L.fwi_strerror.argtypes = [ctypes.c_int]
         L.fwi_strerror.restype = ctypes.c_char_p
+        BP = ctypes.POINTER(fwi_batch_problem)
+        L.fwi_batch_workspace_bytes.argtypes = [ctypes.c_int32, BP, ctypes.POINTER(sz)]
+        L.fwi_batch_plan_create.argtypes = [ctypes.c_int32, BP, vp, sz, ctypes.c_int32, vp,
+                                            ctypes.POINTER(vp)]
+        L.fwi_batch_plan_run.argtypes = [vp, ctypes.c_int32, vp]
+        L.fwi_batch_plan_info.argtypes = [vp, ctypes.POINTER(fwi_batch_info)]
+        L.fwi_batch_plan_destroy.argtypes = [vp]
+        L.fwi_batch_plan_destroy.restype = None
         for name in ("fwi_workspace_bytes", "fwi_checkpoint_interval", "fdtd_forward",
-                     "fdtd_adjoint", "fwi_gradient", "fwi_gradient_timed"):
+                     "fdtd_adjoint", "fwi_gradient", "fwi_gradient_timed",
+                     "fwi_batch_workspace_bytes", "fwi_batch_plan_create", "fwi_batch_plan_run",
+                     "fwi_batch_plan_info"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -251,3 +284,68 @@ def alloc_workspace(nbytes: int, device="cuda"):
     v = t[off:off + int(nbytes)]
     assert v.data_ptr() % 256 == 0
     return v
+
+
+# ---- batched gradients of independent problems -------------------------------
+class BatchProblem:
+    """One problem of a batch: grid, Geometry, and device arrays (kept alive
+    here).  eps_r, sigma [NY][NX]; observed [S][nt][R]; misfit a float64
+    device scalar; grad_eps_r, grad_sigma [NY][NX]."""
+
+    def __init__(self, grid, geom, eps_r, sigma, observed, misfit, grad_eps_r, grad_sigma):
+        self.grid, self.geom = grid, geom
+        self.arrays = (eps_r, sigma, observed, misfit, grad_eps_r, grad_sigma)
+        self.c = fwi_batch_problem(grid, geom.c, _ptr(eps_r), _ptr(sigma), _ptr(observed),
+                                   _ptr(misfit), _ptr(grad_eps_r), _ptr(grad_sigma))
+
+
+def _batch_array(problems):
+    arr = (fwi_batch_problem * len(problems))()
+    for k, p in enumerate(problems):
+        arr[k] = p.c
+    return arr
+
+
+def batch_workspace_bytes(problems) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().fwi_batch_workspace_bytes(len(problems), _batch_array(problems),
+                                           ctypes.byref(out)), "fwi_batch_workspace_bytes")
+    return out.value
+
+
+class BatchPlan:
+    """A plan over `problems` (a list of BatchProblem) in workspace `ws`.
+    run() evaluates every problem's misfit and gradient (asynchronous on the
+    stream); close() releases the plan."""
+
+    def __init__(self, problems, ws, autotune=True, stream=None):
+        self.problems = list(problems)
+        self.ws = ws
+        self._arr = _batch_array(self.problems)
+        h = ctypes.c_void_p()
+        _check(lib().fwi_batch_plan_create(len(self.problems), self._arr, _wsptr(ws),
+                                           _nbytes(ws), int(bool(autotune)), _stream(stream),
+                                           ctypes.byref(h)), "fwi_batch_plan_create")
+        self._h = h
+
+    def run(self, use_graph=True, stream=None):
+        if not self._h:
+            raise RuntimeError("plan is closed")
+        _check(lib().fwi_batch_plan_run(self._h, int(bool(use_graph)), _stream(stream)),
+               "fwi_batch_plan_run")
+
+    def info(self) -> dict:
+        i = fwi_batch_info()
+        _check(lib().fwi_batch_plan_info(self._h, ctypes.byref(i)), "fwi_batch_plan_info")
+        return i.as_dict()
+
+    def close(self):
+        if self._h:
+            lib().fwi_batch_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

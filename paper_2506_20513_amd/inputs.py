@@ -99,6 +99,22 @@ def config_large() -> RunConfig:
     return RunConfig("large-2048x1024", 2048, 1024, 20, 6000, 0.005, 0.005, 400e6, 64, 256)
 
 
+def config_uneven(n_models: int = 96, seed: int = 5) -> list[RunConfig]:
+    """Independent problems of uneven size for the batched gradient: interior
+    nx uniform in [200, 640] and ny in [100, 320] cells, dx = dy = 0.01 m,
+    nt uniform in [1500, 4000], 20-cell CPML, 8 shots x 64 surface
+    receivers, Ricker 200 MHz; models as in the 128x128 workload (seeded per
+    problem)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for m in range(n_models):
+        nx = int(rng.integers(200, 641))
+        ny = int(rng.integers(100, 321))
+        nt = int(rng.integers(1500, 4001))
+        out.append(RunConfig(f"uneven-{m}-{nx}x{ny}", nx, ny, 20, nt, 0.01, 0.01, 200e6, 8, 64))
+    return out
+
+
 def config_paper_shapes() -> list[RunConfig]:
     """Grid shapes of the paper's three experiments (Tables 2-4), none a
     multiple of 64, used as odd-shape cases.  Step counts shortened."""
@@ -253,6 +269,11 @@ def model_for(cfg: RunConfig, seed: int | None = None):
     """(true eps_r, true sigma, initial eps_r, initial sigma) for a config."""
     if cfg.name.startswith("tiny"):
         e, s = model_tiny(cfg, 1 if seed is None else seed)
+        e0, s0 = smooth_model(e, s, cfg.npml, 6.0)
+        return e, s, e0, s0
+    if cfg.name.startswith("uneven"):
+        k = int(cfg.name.split("-")[1])
+        e, s = model_tiny(cfg, 1000 + k if seed is None else seed)
         e0, s0 = smooth_model(e, s, cfg.npml, 6.0)
         return e, s, e0, s0
     if cfg.name.startswith("survey"):

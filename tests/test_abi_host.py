@@ -188,3 +188,41 @@ def test_adjoint_and_gradient_argument_checks():
     assert L.fwi_workspace_bytes(ctypes.byref(grid), ctypes.byref(geom.c), 0, None) == fwi.FWI_EINVAL
     assert L.fwi_workspace_bytes(None, ctypes.byref(geom.c), 0,
                                  ctypes.byref(ctypes.c_size_t())) == fwi.FWI_EINVAL
+
+
+def _batch_problem(grid, geom, ptr=FAKE):
+    return fwi.fwi_batch_problem(grid, geom.c, ptr, ptr, ptr, ptr, ptr, ptr)
+
+
+def test_batch_argument_checks():
+    """Batched plans validate every problem on the host, before any HIP call."""
+    _, grid, geom = _tiny()
+    L = fwi.lib()
+    out = ctypes.c_size_t()
+    arr = (fwi.fwi_batch_problem * 2)(_batch_problem(grid, geom), _batch_problem(grid, geom))
+    assert L.fwi_batch_workspace_bytes(2, arr, ctypes.byref(out)) == fwi.FWI_OK
+    one = (fwi.fwi_batch_problem * 1)(_batch_problem(grid, geom))
+    out1 = ctypes.c_size_t()
+    assert L.fwi_batch_workspace_bytes(1, one, ctypes.byref(out1)) == fwi.FWI_OK
+    assert out.value > out1.value > 0
+    assert L.fwi_batch_workspace_bytes(0, arr, ctypes.byref(out)) == fwi.FWI_EINVAL
+    assert L.fwi_batch_workspace_bytes(2, arr, None) == fwi.FWI_EINVAL
+    bad = (fwi.fwi_batch_problem * 2)(_batch_problem(grid, geom), _batch_problem(grid, geom, 0))
+    assert L.fwi_batch_workspace_bytes(2, bad, ctypes.byref(out)) == fwi.FWI_EINVAL
+    g2 = fwi_grid_copy(grid)
+    g2.dt = grid.dt * 10
+    cfl = (fwi.fwi_batch_problem * 2)(_batch_problem(grid, geom), _batch_problem(g2, geom))
+    assert L.fwi_batch_workspace_bytes(2, cfl, ctypes.byref(out)) == fwi.FWI_ECFL
+    # a workspace that is too small (or missing) is refused before any HIP call
+    plan = ctypes.c_void_p()
+    assert L.fwi_batch_plan_create(2, arr, FAKE, out.value - 1, 1, None,
+                                   ctypes.byref(plan)) == fwi.FWI_ENOMEM
+    assert L.fwi_batch_plan_create(2, arr, None, out.value, 1, None,
+                                   ctypes.byref(plan)) == fwi.FWI_ENOMEM
+    assert not plan.value
+    assert L.fwi_batch_plan_run(None, 1, None) == fwi.FWI_EINVAL
+    L.fwi_batch_plan_destroy(None)
+
+
+def fwi_grid_copy(g):
+    return fwi.fwi_grid.from_buffer_copy(g)
