@@ -1,0 +1,501 @@
+// Kernels of the learned gradient preconditioner: a small encoder-decoder
+// CNN with 3x3 convolutions on BF16 activations and weights, FP32
+// accumulation on the gfx950 matrix cores (v_mfma_f32_16x16x32_bf16).
+//
+// Layouts: activations NHWC [N][H][W][C] bf16 with C a multiple of 32;
+// weights [Co][3][3][Ci] bf16 (FP32 masters held by the optimiser); all
+// convolutions are 3x3, stride 1, zero padding 1.
+//
+// MFMA 16x16x32 operand layout (lane l of the wave): A holds row l%16,
+// columns 8*(l/16) .. +7; B holds rows 8*(l/16) .. +7 of column l%16; the
+// 16x16 result holds rows 4*(l/16) .. +3 of column l%16.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fwi_nn.h"
+
+namespace {
+
+using bf16 = __bf16;
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// y = act(conv3x3(x, w) + bias) as an implicit GEMM: rows are output pixels,
+// columns output channels, the reduction runs over (ky, kx, ci).  A block of
+// four waves covers 64 pixels of one image row; wave w its 16 pixels times
+// 16*NT output channels (NT tiles of 16).
+template <int NT>
+__global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ x,
+                                                 const bf16 *__restrict__ w,
+                                                 const float *__restrict__ bias,
+                                                 bf16 *__restrict__ y, int N, int H, int W,
+                                                 int Ci, int Co, int relu) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int xblocks = (W + 63) / 64;
+    int b = blockIdx.x;
+    const int xb = b % xblocks;
+    b /= xblocks;
+    const int row = b % H, n = b / H;
+    const int co0 = blockIdx.y * (16 * NT);
+    const int px = xb * 64 + wave * 16 + (lane & 15);
+    const int kq = (lane >> 4) * 8;
+    f32x4 acc[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16x8 zero{};
+    for (int ky = 0; ky < 3; ++ky) {
+        const int yy = row + ky - 1;
+        for (int kx = 0; kx < 3; ++kx) {
+            const int xx = px + kx - 1;
+            const bool ok = yy >= 0 && yy < H && xx >= 0 && xx < W && px < W;
+            // out-of-image taps read a valid address and are zeroed
+            const bf16 *xp = x + (ok ? (((size_t)n * H + yy) * W + xx) * Ci : 0) + kq;
+            const bf16 *wp = w + ((size_t)(co0 + (lane & 15)) * 9 + ky * 3 + kx) * Ci + kq;
+            for (int c0 = 0; c0 < Ci; c0 += 32) {
+                bf16x8 a = *reinterpret_cast<const bf16x8 *>(xp + c0);
+                if (!ok) a = zero;
+#pragma unroll
+                for (int j = 0; j < NT; ++j) {
+                    const bf16x8 bv =
+                        *reinterpret_cast<const bf16x8 *>(wp + (size_t)j * 16 * 9 * Ci + c0);
+                    acc[j] = mfma(a, bv, acc[j]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int co = co0 + 16 * j + (lane & 15);
+        const float bb = bias ? bias[co] : 0.f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int pxo = xb * 64 + wave * 16 + 4 * (lane >> 4) + r;
+            if (pxo < W) {
+                float v = acc[j][r] + bb;
+                if (relu) v = fmaxf(v, 0.f);
+                y[(((size_t)n * H + row) * W + pxo) * Co + co] = (bf16)v;
+            }
+        }
+    }
+}
+
+// wf[ci][ky][kx][co] = w[co][2-ky][2-kx][ci]: the weights of the transposed
+// convolution (input gradient = conv3x3(output gradient, wf)).
+__global__ void k_flip(const bf16 *__restrict__ w, bf16 *__restrict__ wf, int Ci, int Co) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= Co * 9 * Ci) return;
+    const int ci = t % Ci, k = (t / Ci) % 9, co = t / (9 * Ci);
+    const int ky = k / 3, kx = k % 3;
+    wf[((size_t)ci * 9 + (2 - ky) * 3 + (2 - kx)) * Co + co] = w[t];
+}
+
+// ---------------------------------------------------------------------------
+// Weight and bias gradients: dw[co][ky][kx][ci] = sum_p dz[p][co] x[p + (ky-1, kx-1)][ci],
+// db[co] = sum_p dz[p][co].  GEMM with the pixels as reduction: a block owns
+// a 32 (co) x 32 (ci) tile of one tap, loops over every gridDim.x-th chunk
+// of 32 pixels and writes its partial sums to part[blockIdx.x]; each chunk's
+// tiles go through LDS transposed so the pixels are contiguous per channel.
+constexpr int kPitch = 40;   // LDS row: 32 pixels + 8 padding (80 bytes, 16-byte aligned)
+
+__global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ x,
+                                               const bf16 *__restrict__ dz,
+                                               float *__restrict__ part,
+                                               float *__restrict__ bpart, int N, int H, int W,
+                                               int Ci, int Co) {
+    __shared__ __attribute__((aligned(16))) bf16 zt[32][kPitch];   // [co][px]
+    __shared__ __attribute__((aligned(16))) bf16 xt[32][kPitch];   // [ci][px]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = threadIdx.x;
+    const int nci = Ci / 32;
+    int g = blockIdx.y;
+    const int cit = g % nci;
+    g /= nci;
+    const int tap = g % 9, cot = g / 9;
+    const int ky = tap / 3, kx = tap % 3;
+    const size_t P = (size_t)N * H * W;
+    const size_t nchunk = (P + 31) / 32;
+    const int mt = wave >> 1, nt = wave & 1;      // this wave's 16x16 sub-tile
+    f32x4 acc{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;                               // bias partial (tap 0, ci tile 0)
+    const bool do_bias = tap == 0 && cit == 0;
+    // fill role: pixel fp = t >> 3, channels fc .. fc+3
+    const int fp = t >> 3, fc = (t & 7) * 4;
+    for (size_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+        const size_t p = ch * 32 + fp;
+        bf16 zv[4] = {(bf16)0.f, (bf16)0.f, (bf16)0.f, (bf16)0.f};
+        bf16 xv[4] = {(bf16)0.f, (bf16)0.f, (bf16)0.f, (bf16)0.f};
+        if (p < P) {
+            const bf16 *zp = dz + p * Co + cot * 32 + fc;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) zv[i] = zp[i];
+            const int px = (int)(p % W), py = (int)((p / W) % H);
+            const size_t pn = p / ((size_t)W * H);
+            const int xx = px + kx - 1, yy = py + ky - 1;
+            if (xx >= 0 && xx < W && yy >= 0 && yy < H) {
+                const bf16 *xp = x + ((pn * H + yy) * W + xx) * Ci + cit * 32 + fc;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) xv[i] = xp[i];
+            }
+        }
+        __syncthreads();   // previous chunk's reads done
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            zt[fc + i][fp] = zv[i];
+            xt[fc + i][fp] = xv[i];
+        }
+        __syncthreads();
+        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&zt[16 * mt + (lane & 15)][8 * (lane >> 4)]);
+        const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&xt[16 * nt + (lane & 15)][8 * (lane >> 4)]);
+        acc = mfma(a, bv, acc);
+        if (do_bias && t < 32) {
+#pragma unroll 8
+            for (int q = 0; q < 32; ++q) bsum += (float)zt[t][q];
+        }
+    }
+    // partial tile of this block
+    const size_t tile = (size_t)Co * 9 * Ci;
+    float *o = part + blockIdx.x * tile;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int co = cot * 32 + 16 * mt + 4 * (lane >> 4) + r;
+        const int ci = cit * 32 + 16 * nt + (lane & 15);
+        o[((size_t)co * 9 + tap) * Ci + ci] = acc[r];
+    }
+    if (do_bias && t < 32) bpart[(size_t)blockIdx.x * Co + cot * 32 + t] = bsum;
+}
+
+// out[i] = sum_k part[k][i] in fixed order k = 0 .. nsplit-1
+__global__ void k_reduce(const float *__restrict__ part, float *__restrict__ out, size_t n,
+                         int nsplit) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int k = 0; k < nsplit; ++k) s += part[(size_t)k * n + i];
+    out[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Element-wise pieces.
+__global__ void k_relu_bwd(const bf16 *__restrict__ y, const bf16 *__restrict__ dy,
+                           bf16 *__restrict__ dz, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dz[i] = (float)y[i] > 0.f ? dy[i] : (bf16)0.f;
+}
+
+// 2x2 average pooling (H, W even) and its adjoint
+__global__ void k_pool(const bf16 *__restrict__ x, bf16 *__restrict__ y, int N, int H, int W,
+                       int C) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int Ho = H / 2, Wo = W / 2;
+    if (i >= (size_t)N * Ho * Wo * C) return;
+    const int c = (int)(i % C);
+    size_t r = i / C;
+    const int xo = (int)(r % Wo), yo = (int)((r / Wo) % Ho);
+    const size_t n = r / ((size_t)Wo * Ho);
+    const bf16 *p = x + ((n * H + 2 * yo) * W + 2 * xo) * C + c;
+    const float s = (float)p[0] + (float)p[C] + (float)p[(size_t)W * C] + (float)p[(size_t)W * C + C];
+    y[i] = (bf16)(0.25f * s);
+}
+__global__ void k_pool_bwd(const bf16 *__restrict__ dy, bf16 *__restrict__ dx, int N, int H,
+                           int W, int C) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)N * H * W * C) return;
+    const int c = (int)(i % C);
+    size_t r = i / C;
+    const int xx = (int)(r % W), yy = (int)((r / W) % H);
+    const size_t n = r / ((size_t)W * H);
+    dx[i] = (bf16)(0.25f * (float)dy[((n * (H / 2) + yy / 2) * (W / 2) + xx / 2) * C + c]);
+}
+
+// nearest 2x upsampling plus a skip: y = up(x) + s (s may be null), and the
+// adjoint of the upsampling (sum of each 2x2 block)
+__global__ void k_up_add(const bf16 *__restrict__ x, const bf16 *__restrict__ s,
+                         bf16 *__restrict__ y, int N, int Ho, int Wo, int C) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)N * Ho * Wo * C) return;
+    const int c = (int)(i % C);
+    size_t r = i / C;
+    const int xx = (int)(r % Wo), yy = (int)((r / Wo) % Ho);
+    const size_t n = r / ((size_t)Wo * Ho);
+    float v = (float)x[((n * (Ho / 2) + yy / 2) * (Wo / 2) + xx / 2) * C + c];
+    if (s) v += (float)s[i];
+    y[i] = (bf16)v;
+}
+__global__ void k_up_bwd(const bf16 *__restrict__ dy, bf16 *__restrict__ dx, int N, int Hi,
+                         int Wi, int C) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)N * Hi * Wi * C) return;
+    const int c = (int)(i % C);
+    size_t r = i / C;
+    const int xx = (int)(r % Wi), yy = (int)((r / Wi) % Hi);
+    const size_t n = r / ((size_t)Wi * Hi);
+    const int W2 = 2 * Wi;
+    const bf16 *p = dy + ((n * 2 * Hi + 2 * yy) * W2 + 2 * xx) * C + c;
+    dx[i] = (bf16)((float)p[0] + (float)p[C] + (float)p[(size_t)W2 * C] +
+                   (float)p[(size_t)W2 * C + C]);
+}
+
+__global__ void k_add(const bf16 *a, const bf16 *b,
+                      bf16 *y, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (bf16)((float)a[i] + (float)b[i]);
+}
+
+// Mean squared error over the first `cout` channels of y [P][C] against
+// target [P][cout] (FP32): per-block partial sums (double) and the gradient
+// dy = 2 (y - t) / (P cout) (zero in the other channels).
+__global__ __launch_bounds__(256) void k_mse(const bf16 *__restrict__ y,
+                                             const float *__restrict__ tgt,
+                                             bf16 *__restrict__ dy, double *__restrict__ partial,
+                                             size_t P, int C, int cout) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    const double scale = 2.0 / ((double)P * cout);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < P * C;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        const size_t p = i / C;
+        float g = 0.f;
+        if (c < cout) {
+            const double d = (double)(float)y[i] - (double)tgt[p * cout + c];
+            acc += d * d;
+            g = (float)(scale * d);
+        }
+        if (dy) dy[i] = (bf16)g;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+__global__ void k_sum(const double *__restrict__ partial, int n, double scale,
+                      double *__restrict__ out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += partial[i];
+        *out = s * scale;
+    }
+}
+
+// Adam on FP32 masters with a BF16 copy for the kernels (bf16 may be null).
+__global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, bf16 *__restrict__ wb, size_t n, float lr,
+                       float b1, float b2, float eps, float c1, float c2) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    if (wb) wb[i] = (bf16)wi;
+}
+
+__global__ void k_to_bf16(const float *__restrict__ a, bf16 *__restrict__ b, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (bf16)a[i];
+}
+
+// Network input / output conversion between float32 planes and NHWC bf16.
+__global__ void k_pack4(const float *__restrict__ planes, const float *__restrict__ scale,
+                        bf16 *__restrict__ x, int N, int H, int W, int C) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)N * H * W * C) return;
+    const int c = (int)(i % C);
+    const size_t p = i / C;               // pixel index n*H*W + y*W + x
+    const size_t hw = (size_t)H * W;
+    const size_t n = p / hw, q = p % hw;
+    x[i] = c < 4 ? (bf16)(planes[(n * 4 + c) * hw + q] * scale[n * 4 + c]) : (bf16)0.f;
+}
+__global__ void k_unpack2(const bf16 *__restrict__ y, const float *__restrict__ scale,
+                          float *__restrict__ out, int N, int H, int W, int C) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t hw = (size_t)H * W;
+    if (i >= (size_t)N * 2 * hw) return;
+    const size_t q = i % hw, nc = i / hw;
+    const int c = (int)(nc % 2);
+    const size_t n = nc / 2;
+    out[i] = (float)y[(n * hw + q) * C + c] * scale[n * 2 + c];
+}
+
+unsigned blocks_for(size_t n) { return (unsigned)((n + 255) / 256); }
+
+int status(hipError_t e) { return e == hipSuccess ? FWI_NN_OK : FWI_NN_EHIP; }
+
+bool al16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+int fwi_nn_conv3x3(const void *x, const void *w, const float *bias, void *y, int32_t N,
+                   int32_t H, int32_t W, int32_t Ci, int32_t Co, int32_t relu, void *stream) {
+    if (!x || !w || !y || N < 1 || H < 1 || W < 1 || Ci < 32 || Co < 32 || Ci % 32 || Co % 32 ||
+        !al16(x) || !al16(w))
+        return FWI_NN_EINVAL;
+    if ((int64_t)N * H > (int64_t)1 << 30) return FWI_NN_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const unsigned gx = (unsigned)(N * H * ((W + 63) / 64));
+    const bf16 *xb = static_cast<const bf16 *>(x);
+    const bf16 *wb = static_cast<const bf16 *>(w);
+    bf16 *yb = static_cast<bf16 *>(y);
+    if (Co % 64 == 0)
+        hipLaunchKernelGGL(k_conv3x3<4>, dim3(gx, Co / 64), dim3(256), 0, st, xb, wb, bias, yb, N,
+                           H, W, Ci, Co, relu);
+    else
+        hipLaunchKernelGGL(k_conv3x3<2>, dim3(gx, Co / 32), dim3(256), 0, st, xb, wb, bias, yb, N,
+                           H, W, Ci, Co, relu);
+    return status(hipGetLastError());
+}
+
+int fwi_nn_flip(const void *w, void *wf, int32_t Ci, int32_t Co, void *stream) {
+    if (!w || !wf || Ci < 1 || Co < 1) return FWI_NN_EINVAL;
+    const size_t n = (size_t)Co * 9 * Ci;
+    hipLaunchKernelGGL(k_flip, dim3(blocks_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       static_cast<const bf16 *>(w), static_cast<bf16 *>(wf), Ci, Co);
+    return status(hipGetLastError());
+}
+
+size_t fwi_nn_wgrad_workspace(int32_t Ci, int32_t Co, int32_t nsplit) {
+    return ((size_t)nsplit * Co * 9 * Ci + (size_t)nsplit * Co) * sizeof(float);
+}
+
+int fwi_nn_wgrad(const void *x, const void *dz, float *dw, float *db, int32_t N, int32_t H,
+                 int32_t W, int32_t Ci, int32_t Co, int32_t nsplit, void *ws, size_t ws_bytes,
+                 void *stream) {
+    if (!x || !dz || !dw || !db || !ws || N < 1 || H < 1 || W < 1 || Ci < 32 || Co < 32 ||
+        Ci % 32 || Co % 32 || nsplit < 1 || nsplit > 65535 ||
+        ws_bytes < fwi_nn_wgrad_workspace(Ci, Co, nsplit))
+        return FWI_NN_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    float *part = static_cast<float *>(ws);
+    float *bpart = part + (size_t)nsplit * Co * 9 * Ci;
+    hipLaunchKernelGGL(k_wgrad, dim3(nsplit, (Co / 32) * 9 * (Ci / 32)), dim3(256), 0, st,
+                       static_cast<const bf16 *>(x), static_cast<const bf16 *>(dz), part, bpart, N,
+                       H, W, Ci, Co);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return FWI_NN_EHIP;
+    const size_t nw = (size_t)Co * 9 * Ci;
+    hipLaunchKernelGGL(k_reduce, dim3(blocks_for(nw)), dim3(256), 0, st, part, dw, nw, nsplit);
+    hipLaunchKernelGGL(k_reduce, dim3(blocks_for(Co)), dim3(256), 0, st, bpart, db, (size_t)Co,
+                       nsplit);
+    return status(hipGetLastError());
+}
+
+int fwi_nn_relu_bwd(const void *y, const void *dy, void *dz, size_t n, void *stream) {
+    if (!y || !dy || !dz) return FWI_NN_EINVAL;
+    if (n == 0) return FWI_NN_OK;
+    hipLaunchKernelGGL(k_relu_bwd, dim3(blocks_for(n)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), static_cast<const bf16 *>(y),
+                       static_cast<const bf16 *>(dy), static_cast<bf16 *>(dz), n);
+    return status(hipGetLastError());
+}
+
+int fwi_nn_pool2(const void *x, void *y, int32_t N, int32_t H, int32_t W, int32_t C, void *stream) {
+    if (!x || !y || N < 1 || H < 2 || W < 2 || H % 2 || W % 2 || C < 1) return FWI_NN_EINVAL;
+    const size_t n = (size_t)N * (H / 2) * (W / 2) * C;
+    hipLaunchKernelGGL(k_pool, dim3(blocks_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       static_cast<const bf16 *>(x), static_cast<bf16 *>(y), N, H, W, C);
+    return status(hipGetLastError());
+}
+
+int fwi_nn_pool2_bwd(const void *dy, void *dx, int32_t N, int32_t H, int32_t W, int32_t C,
+                     void *stream) {
+    if (!dy || !dx || N < 1 || H < 2 || W < 2 || H % 2 || W % 2 || C < 1) return FWI_NN_EINVAL;
+    const size_t n = (size_t)N * H * W * C;
+    hipLaunchKernelGGL(k_pool_bwd, dim3(blocks_for(n)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), static_cast<const bf16 *>(dy),
+                       static_cast<bf16 *>(dx), N, H, W, C);
+    return status(hipGetLastError());
+}
+
+int fwi_nn_up2_add(const void *x, const void *skip, void *y, int32_t N, int32_t Ho, int32_t Wo,
+                   int32_t C, void *stream) {
+    if (!x || !y || N < 1 || Ho < 2 || Wo < 2 || Ho % 2 || Wo % 2 || C < 1) return FWI_NN_EINVAL;
+    const size_t n = (size_t)N * Ho * Wo * C;
+    hipLaunchKernelGGL(k_up_add, dim3(blocks_for(n)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), static_cast<const bf16 *>(x),
+                       static_cast<const bf16 *>(skip), static_cast<bf16 *>(y), N, Ho, Wo, C);
+    return status(hipGetLastError());
+}
+
+int fwi_nn_up2_bwd(const void *dy, void *dx, int32_t N, int32_t Hi, int32_t Wi, int32_t C,
+                   void *stream) {
+    if (!dy || !dx || N < 1 || Hi < 1 || Wi < 1 || C < 1) return FWI_NN_EINVAL;
+    const size_t n = (size_t)N * Hi * Wi * C;
+    hipLaunchKernelGGL(k_up_bwd, dim3(blocks_for(n)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), static_cast<const bf16 *>(dy),
+                       static_cast<bf16 *>(dx), N, Hi, Wi, C);
+    return status(hipGetLastError());
+}
+
+int fwi_nn_add(const void *a, const void *b, void *y, size_t n, void *stream) {
+    if (!a || !b || !y) return FWI_NN_EINVAL;
+    if (n == 0) return FWI_NN_OK;
+    hipLaunchKernelGGL(k_add, dim3(blocks_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       static_cast<const bf16 *>(a), static_cast<const bf16 *>(b),
+                       static_cast<bf16 *>(y), n);
+    return status(hipGetLastError());
+}
+
+int fwi_nn_mse(const void *y, const float *target, void *dy, double *loss, double *partials,
+               size_t P, int32_t C, int32_t cout, void *stream) {
+    if (!y || !target || !loss || !partials || P == 0 || C < 1 || cout < 1 || cout > C)
+        return FWI_NN_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_mse, dim3(FWI_NN_MSE_BLOCKS), dim3(256), 0, st,
+                       static_cast<const bf16 *>(y), target, static_cast<bf16 *>(dy), partials, P,
+                       C, cout);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(64), 0, st, partials, FWI_NN_MSE_BLOCKS,
+                       1.0 / ((double)P * cout), loss);
+    return status(hipGetLastError());
+}
+
+int fwi_nn_adam(float *w, const float *g, float *m, float *v, void *wb, size_t n, float lr,
+                float beta1, float beta2, float eps, int32_t step, void *stream) {
+    if (!w || !g || !m || !v || step < 1) return FWI_NN_EINVAL;
+    if (n == 0) return FWI_NN_OK;
+    const float c1 = 1.f - powf(beta1, (float)step), c2 = 1.f - powf(beta2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       w, g, m, v, static_cast<bf16 *>(wb), n, lr, beta1, beta2, eps, c1, c2);
+    return status(hipGetLastError());
+}
+
+int fwi_nn_to_bf16(const float *a, void *b, size_t n, void *stream) {
+    if (!a || !b) return FWI_NN_EINVAL;
+    if (n == 0) return FWI_NN_OK;
+    hipLaunchKernelGGL(k_to_bf16, dim3(blocks_for(n)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), a, static_cast<bf16 *>(b), n);
+    return status(hipGetLastError());
+}
+
+int fwi_nn_pack4(const float *planes, const float *scale, void *x, int32_t N, int32_t H,
+                 int32_t W, int32_t C, void *stream) {
+    if (!planes || !scale || !x || N < 1 || H < 1 || W < 1 || C < 4) return FWI_NN_EINVAL;
+    const size_t n = (size_t)N * H * W * C;
+    hipLaunchKernelGGL(k_pack4, dim3(blocks_for(n)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), planes, scale, static_cast<bf16 *>(x), N,
+                       H, W, C);
+    return status(hipGetLastError());
+}
+
+int fwi_nn_unpack2(const void *y, const float *scale, float *out, int32_t N, int32_t H,
+                   int32_t W, int32_t C, void *stream) {
+    if (!y || !scale || !out || N < 1 || H < 1 || W < 1 || C < 2) return FWI_NN_EINVAL;
+    const size_t n = (size_t)N * 2 * H * W;
+    hipLaunchKernelGGL(k_unpack2, dim3(blocks_for(n)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), static_cast<const bf16 *>(y), scale, out,
+                       N, H, W, C);
+    return status(hipGetLastError());
+}
+
+}  // extern "C"

@@ -1,0 +1,542 @@
+"""Learned gradient preconditioner for the dual-parameter FWI (Sec. 3.3 of
+arXiv 2506.20513: eps_r and sigma from the trace misfit Eq. (6) with the
+adjoint gradients Eqs. (12)-(13)).
+
+The paper has no learned component; this module adds one on top of its
+inversion.
+
+1. Plain L-BFGS FWI runs on seeded 128x128 models generate pairs.  Each pair
+   maps the state at iterate k (grad_eps, grad_sigma, eps_r, sigma) to the
+   update the run makes from there to its final iterate K.
+2. The encoder-decoder CNN of `nn` (BF16 MFMA kernels, FP32 accumulation)
+   is trained on those pairs with Adam.
+3. Inside an inversion, the network proposes a step at every iterate.  The
+   objective decrease judges the proposal: it needs a descent direction and
+   at least a tenth of the decrease its slope predicts, within two trial
+   lengths.  Otherwise the plain L-BFGS step is taken.  Both kinds of steps
+   feed the same L-BFGS curvature memory.  After two failed proposals in a
+   row the run continues as plain L-BFGS.
+
+Network input at iterate k: the two gradient planes divided by the rms of
+the run's first gradient (so the input shows how far the gradient has
+shrunk), and the two model planes u, v.
+
+Units: the optimiser works on the interior models normalised as in fwi_loop
+(u = eps_r / eps_scale, v = sigma / sig_scale), on x = [u; v] flattened.
+The rows just below the surface stay fixed, and every iterate is projected
+onto eps_r >= eps_min, sigma >= sig_min.
+
+    python -m paper_2506_20513_amd.precond --runs 667 --iters 30 --epochs 8
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import autograd as AG
+from . import fwi_loop as FL
+from . import nn
+
+
+# ---------------------------------------------------------------------------
+# Objective on normalised interior models
+# ---------------------------------------------------------------------------
+class Objective:
+    """f(x) = J(m(x)) / J0 + tv_weight (TV(u) + TV(v)) and its gradient.
+
+    J is the trace misfit of Eq. (6) and J0 its value at the initial model.
+    x is flat [u; v] over the interior (ny * nx each).  The gradient is zero
+    on the fixed surface rows."""
+
+    def __init__(self, prob: AG.Problem, observed: torch.Tensor, eps0: torch.Tensor,
+                 sig0: torch.Tensor, st: FL.Settings):
+        self.prob, self.obs, self.st = prob, observed.contiguous(), st
+        self.npml = prob.grid.npml
+        NY, NX = prob.model_shape
+        self.ny, self.nx = NY - 2 * self.npml, NX - 2 * self.npml
+        sl = (slice(self.npml, NY - self.npml), slice(self.npml, NX - self.npml))
+        self.x0 = torch.cat([(eps0[sl] / st.eps_scale).reshape(-1),
+                             (sig0[sl] / st.sig_scale).reshape(-1)]).contiguous()
+        self.free = torch.ones(self.ny, self.nx, dtype=torch.bool, device=eps0.device)
+        self.free[: st.mask_rows] = False
+        self.free = torch.cat([self.free.reshape(-1), self.free.reshape(-1)])
+        n = self.ny * self.nx
+        self.lo = torch.cat([torch.full((n,), st.eps_min / st.eps_scale, device=eps0.device),
+                             torch.full((n,), st.sig_min / st.sig_scale, device=eps0.device)])
+        self.J0 = None
+        self.evals = 0
+        self.last_J = None
+
+    def project(self, x):
+        x = torch.where(self.free, x, self.x0)
+        return torch.maximum(x, self.lo)
+
+    def planes(self, x):
+        n = self.ny * self.nx
+        return x[:n].view(self.ny, self.nx), x[n:].view(self.ny, self.nx)
+
+    def models(self, x):
+        u, v = self.planes(x)
+        return (FL.pad_interior(u * self.st.eps_scale, self.npml).contiguous(),
+                FL.pad_interior(v * self.st.sig_scale, self.npml).contiguous())
+
+    def __call__(self, x):
+        xx = x.detach().clone().requires_grad_(True)
+        e, s = self.models(xx)
+        J = AG.misfit(self.prob, e, s, self.obs)
+        if self.J0 is None:
+            self.J0 = float(J.detach())
+        u, v = self.planes(xx)
+        loss = J / self.J0 + self.st.tv_weight * (FL.total_variation(u) + FL.total_variation(v))
+        loss.backward()
+        self.evals += 1
+        self.last_J = float(J.detach())
+        g = torch.where(self.free, xx.grad, torch.zeros_like(xx.grad))
+        return float(loss.detach()), g
+
+
+# ---------------------------------------------------------------------------
+# L-BFGS (two-loop recursion, Nocedal and Wright Alg. 7.4) with a projected
+# Armijo backtracking line search
+# ---------------------------------------------------------------------------
+class LBFGS:
+    def __init__(self, history: int = 10):
+        self.history = history
+        self.S, self.Y = [], []
+
+    def reset(self):
+        self.S, self.Y = [], []
+
+    def update(self, s, y):
+        """Store the pair if its curvature s.y is positive (keeps H positive
+        definite without a Wolfe curvature condition)."""
+        sy = float(torch.dot(s, y))
+        if sy > 1e-12 * float(torch.dot(y, y)) and sy > 0:
+            self.S.append(s)
+            self.Y.append(y)
+            if len(self.S) > self.history:
+                self.S.pop(0)
+                self.Y.pop(0)
+
+    def direction(self, g):
+        """-H g with the limited-memory inverse Hessian H (initial scaling
+        s.y / y.y of the newest pair); None without stored pairs."""
+        if not self.S:
+            return None
+        q = g.clone()
+        alpha = []
+        for s, y in zip(reversed(self.S), reversed(self.Y)):
+            a = float(torch.dot(s, q)) / float(torch.dot(y, s))
+            q -= a * y
+            alpha.append(a)
+        s, y = self.S[-1], self.Y[-1]
+        r = q * (float(torch.dot(s, y)) / float(torch.dot(y, y)))
+        for (s, y), a in zip(zip(self.S, self.Y), reversed(alpha)):
+            b = float(torch.dot(y, r)) / float(torch.dot(y, s))
+            r += (a - b) * s
+        return -r
+
+
+def line_search(obj, x, f, g, d, t0=1.0, trials=8, c1=1e-4, shrink=0.25):
+    """Projected backtracking: accept t if f(P(x + t d)) <= f + c1 g.(P(x + t d) - x).
+    Returns (x_new, f_new, g_new, t) or None."""
+    t = t0
+    for _ in range(trials):
+        xn = obj.project(x + t * d)
+        step = xn - x
+        dec = float(torch.dot(g, step))
+        if dec >= 0:          # the projection removed every descent component
+            return None
+        fn, gn = obj(xn)
+        if fn <= f + c1 * dec:
+            return xn, fn, gn, t
+        t *= shrink
+    return None
+
+
+def proposal_search(obj, x, f, g, d, c1=0.1):
+    """Two trial lengths along a proposed direction d: t = 1, then the
+    minimiser of the quadratic through f(x), the slope g.d and f(x + d)
+    (kept within [0.1, 4]).  A length is accepted if it achieves at least
+    the fraction c1 of the decrease the slope predicts, a stricter test than
+    the Armijo condition of the L-BFGS steps.  Returns (x_new, f_new, g_new,
+    t) or None."""
+    gd = float(torch.dot(g, d))
+    if gd >= 0:
+        return None
+    best = None
+    t = 1.0
+    for trial in range(2):
+        xn = obj.project(x + t * d)
+        dec = float(torch.dot(g, xn - x))
+        if dec >= 0:
+            return None
+        fn, gn = obj(xn)
+        if fn <= f + c1 * dec and (best is None or fn < best[1]):
+            best = (xn, fn, gn, t)
+        if trial == 0:
+            curv = fn - f - gd                 # f(x + t d) ~ f + t gd + t^2 curv
+            if curv <= 0:
+                break                          # still descending at t = 1: keep it
+            ts = min(4.0, max(0.1, -gd / (2.0 * curv)))
+            if best is not None and abs(ts - 1.0) < 0.2:
+                break                          # t = 1 is already near the minimum
+            t = ts
+    return best
+
+
+@dataclass
+class Iterate:
+    k: int
+    f: float
+    J: float
+    evals: int
+    seconds: float
+    source: str          # "start", "lbfgs", "steepest" or "net"
+
+
+@dataclass
+class Run:
+    xs: list = field(default_factory=list)      # iterates (flat, on the GPU)
+    gs: list = field(default_factory=list)      # gradients at the iterates
+    log: list = field(default_factory=list)     # Iterate records
+    seconds: float = 0.0
+
+    @property
+    def final_f(self):
+        return self.log[-1].f
+
+
+def minimise(obj: Objective, iters: int, history: int = 10, first_step: float = 0.05,
+             proposer=None, target_f: float | None = None, keep: bool = False,
+             max_strikes: int = 2) -> Run:
+    """L-BFGS on obj from obj.x0 for `iters` iterations (or until f <=
+    target_f).  proposer(x, g) -> direction or None is tried first at every
+    iterate (proposal_search: at most two evaluations); the decrease it
+    achieves decides, otherwise the L-BFGS step is taken.  After max_strikes
+    proposals in a row fail, the proposer is no longer asked.  keep: retain
+    iterates and gradients (for training pairs)."""
+    torch.cuda.synchronize() if obj.x0.is_cuda else None
+    t0 = time.perf_counter()
+    mem = LBFGS(history)
+    x = obj.project(obj.x0)
+    f, g = obj(x)
+    run = Run()
+
+    def note(k, src):
+        if obj.x0.is_cuda:
+            torch.cuda.synchronize()
+        run.log.append(Iterate(k, f, obj.last_J, obj.evals, time.perf_counter() - t0, src))
+        if keep:
+            run.xs.append(x.clone())
+            run.gs.append(g.clone())
+
+    note(0, "start")
+    strikes = 0
+    for k in range(1, iters + 1):
+        if target_f is not None and f <= target_f:
+            break
+        res, src = None, None
+        if proposer is not None and strikes < max_strikes:
+            d = proposer(x, g)
+            res = proposal_search(obj, x, f, g, d) if d is not None else None
+            src = "net"
+            strikes = 0 if res is not None else strikes + 1
+        if res is None:
+            d = mem.direction(g)
+            src = "lbfgs"
+            if d is None or float(torch.dot(g, d)) >= 0:
+                mem.reset()
+                gmax = float(g.abs().max())
+                if gmax == 0:
+                    break
+                d = -g * (first_step / gmax)
+                src = "steepest"
+            res = line_search(obj, x, f, g, d, t0=1.0)
+            if res is None and src == "lbfgs":
+                mem.reset()
+                d = -g * (first_step / float(g.abs().max()))
+                src = "steepest"
+                res = line_search(obj, x, f, g, d, t0=1.0)
+            if res is None:
+                break
+        xn, fn, gn, _ = res
+        mem.update(xn - x, gn - g)
+        x, f, g = xn, fn, gn
+        note(k, src)
+    run.seconds = run.log[-1].seconds
+    run.x = x
+    return run
+
+
+# ---------------------------------------------------------------------------
+# Features and targets
+# ---------------------------------------------------------------------------
+def gradient_scales(obj: Objective, g0):
+    """1 / rms of the eps_r and sigma parts of the run's first gradient."""
+    n = obj.ny * obj.nx
+    out = []
+    for part in (g0[:n], g0[n:]):
+        r = float(torch.sqrt(torch.mean(part.double() ** 2)))
+        out.append(1.0 / r if r > 0 else 0.0)
+    return out
+
+
+def feature_planes(obj: Objective, x, g, gscale):
+    """[4][ny][nx] float32 (g_u, g_v, u, v) and their scales [4] (gscale
+    for the gradient planes, 1 for the models)."""
+    n = obj.ny * obj.nx
+    planes = torch.stack([g[:n], g[n:], x[:n], x[n:]]).view(4, obj.ny, obj.nx).float()
+    sc = torch.tensor([gscale[0], gscale[1], 1.0, 1.0], dtype=torch.float32, device=x.device)
+    return planes.contiguous(), sc
+
+
+class Preconditioner:
+    """The trained network applied to one iterate: x, g -> proposed step
+    (flat like x, zero on the fixed rows)."""
+
+    def __init__(self, net: nn.Net):
+        self.net = net
+        self.calls = 0
+        self.seconds = 0.0
+        self.gscale = None
+
+    def __call__(self, obj: Objective, x, g):
+        """The first call of a run must be at its starting iterate: its
+        gradient sets the normalisation of the gradient planes."""
+        t = time.perf_counter()
+        if self.gscale is None:
+            self.gscale = gradient_scales(obj, g)
+        planes, sc = feature_planes(obj, x, g, self.gscale)
+        H, W = obj.ny, obj.nx
+        xin = torch.empty(H * W * nn.CPAD, dtype=torch.bfloat16, device=x.device)
+        nn.pack4(planes, sc, xin, 1, H, W)
+        y = self.net.forward(xin, 1, H, W)
+        out = torch.empty(2 * H * W, dtype=torch.float32, device=x.device)
+        nn.unpack2(y, torch.ones(2, device=x.device), out, 1, H, W, nn.CPAD)
+        d = torch.where(obj.free, out.to(x.dtype), torch.zeros_like(x))
+        self.calls += 1
+        self.seconds += time.perf_counter() - t
+        return d
+
+
+# ---------------------------------------------------------------------------
+# Dataset from plain runs
+# ---------------------------------------------------------------------------
+@dataclass
+class Dataset:
+    planes: torch.Tensor     # [M][4][H][W] float32
+    scales: torch.Tensor     # [M][4] float32
+    targets: torch.Tensor    # [M][H][W][2] float32 (normalised units)
+
+    def __len__(self):
+        return self.planes.shape[0]
+
+
+def tiny_problem(seed: int, smoothing: float, device="cuda"):
+    """A seeded 128x128 problem (the small survey-shaped configuration): true
+    model, smoothed start, observed traces, and the autograd problem."""
+    from . import fwi
+    from . import inputs as I
+    cfg = I.config_tiny()
+    e, s = I.model_tiny(cfg, seed)
+    e0, s0 = I.smooth_model(e, s, cfg.npml, smoothing)
+    src, rec = I.geometry(cfg)
+    w = torch.from_numpy(I.wavelets(cfg)).to(device)
+    prob = AG.Problem(fwi.grid_from_config(cfg), src, rec, w, device=device)
+    T = lambda a: torch.from_numpy(a).to(device)
+    with torch.no_grad():
+        obs = AG.traces(prob, T(e), T(s))
+    return cfg, prob, obs, T(e), T(s), T(e0), T(s0)
+
+
+def generate(nruns: int, iters: int, seed0: int, st: FL.Settings, log=print,
+             device="cuda") -> tuple[Dataset, dict]:
+    """Pairs from nruns plain L-BFGS runs on seeded 128x128 models (seeds
+    seed0 .. seed0 + nruns - 1, start models smoothed with a Gaussian of
+    4 to 10 cells).  Pair k of a run: features at iterate k, target x_K - x_k
+    with K the run's last iterate."""
+    planes, scales, targets = [], [], []
+    stats = {"runs": 0, "evaluations": 0, "seconds": 0.0, "final_rel_misfit": []}
+    t0 = time.perf_counter()
+    rng = np.random.default_rng(seed0)
+    for r in range(nruns):
+        cfg, prob, obs, e, s, e0, s0 = tiny_problem(seed0 + r, float(rng.uniform(4.0, 10.0)),
+                                                    device)
+        obj = Objective(prob, obs, e0, s0, st)
+        run = minimise(obj, iters, keep=True)
+        xK = run.xs[-1]
+        n = obj.ny * obj.nx
+        gsc = gradient_scales(obj, run.gs[0])
+        for xk, gk in zip(run.xs[:-1], run.gs[:-1]):
+            p, sc = feature_planes(obj, xk, gk, gsc)
+            planes.append(p)
+            scales.append(sc)
+            dx = (xK - xk).float()
+            targets.append(torch.stack([dx[:n], dx[n:]], dim=-1).view(obj.ny, obj.nx, 2))
+        stats["runs"] += 1
+        stats["evaluations"] += obj.evals
+        stats["final_rel_misfit"].append(run.log[-1].J / obj.J0)
+        if log and (r + 1) % max(1, nruns // 10) == 0:
+            log(f"generate: {r + 1}/{nruns} runs, {len(planes)} pairs, "
+                f"{time.perf_counter() - t0:.1f} s")
+    stats["seconds"] = time.perf_counter() - t0
+    stats["final_rel_misfit"] = float(np.mean(stats["final_rel_misfit"]))
+    return Dataset(torch.stack(planes), torch.stack(scales), torch.stack(targets)), stats
+
+
+def _batch_loss(net: nn.Net, ds: Dataset, idx, xin, dy):
+    b = idx.numel()
+    H, W = ds.planes.shape[2], ds.planes.shape[3]
+    nn.pack4(ds.planes[idx].contiguous(), ds.scales[idx].contiguous(), xin, b, H, W)
+    y = net.forward(xin, b, H, W)
+    return net.loss_and_grad(y, ds.targets[idx].contiguous(), dy, b, H, W)
+
+
+def mean_loss(net: nn.Net, ds: Dataset, ids, batch: int = 32) -> float:
+    """Mean squared error of the network over the pairs `ids`."""
+    H, W = ds.planes.shape[2], ds.planes.shape[3]
+    xin = torch.empty(batch * H * W * nn.CPAD, dtype=torch.bfloat16, device=ds.planes.device)
+    tot = 0.0
+    for i in range(0, ids.numel(), batch):
+        idx = ids[i:i + batch]
+        tot += float(_batch_loss(net, ds, idx, xin, None)) * idx.numel()
+    return tot / max(ids.numel(), 1)
+
+
+def train(ds: Dataset, epochs: int, batch: int = 32, lr: float = 1e-3, seed: int = 0,
+          val_frac: float = 0.05, warmup: int = 100, log=print, device="cuda") -> tuple[nn.Net, dict]:
+    """Adam on the mean squared error between network output and target:
+    linear warm-up over `warmup` steps, then cosine decay to zero.  A
+    fraction val_frac of the pairs is held out for validation."""
+    M = len(ds)
+    g = torch.Generator().manual_seed(seed)
+    perm = torch.randperm(M, generator=g)
+    nval = int(M * val_frac)
+    val, tr = perm[:nval].to(device), perm[nval:].to(device)
+    H, W = ds.planes.shape[2], ds.planes.shape[3]
+    net = nn.Net(seed=seed, device=device)
+    xin = torch.empty(batch * H * W * nn.CPAD, dtype=torch.bfloat16, device=device)
+    dy = torch.empty(batch * H * W * nn.CPAD, dtype=torch.bfloat16, device=device)
+    hist = {"epochs": [], "zero_predictor_val": None, "train_ids": tr, "val_ids": val}
+    if nval:
+        hist["zero_predictor_val"] = float((ds.targets[val].double() ** 2).mean())
+    t0 = time.perf_counter()
+    steps = 0
+    nb = tr.numel() // batch
+    total = max(1, epochs * nb)
+    warmup = min(warmup, max(1, total // 10))
+    for ep in range(epochs):
+        order = tr[torch.randperm(tr.numel(), generator=g).to(device)]
+        losses = torch.zeros(max(nb, 1), dtype=torch.float64, device=device)
+        for i in range(nb):
+            idx = order[i * batch:(i + 1) * batch]
+            losses[i] = _batch_loss(net, ds, idx, xin, dy)[0]
+            net.backward(dy)
+            f = min(1.0, (steps + 1) / warmup) * 0.5 * (1.0 + math.cos(math.pi * steps / total))
+            net.adam_step(lr * f)
+            steps += 1
+        vl = mean_loss(net, ds, val, batch) if nval else float("nan")
+        torch.cuda.synchronize()
+        rec = {"epoch": ep + 1, "train_loss": float(losses.mean()), "val_loss": vl,
+               "seconds": time.perf_counter() - t0}
+        hist["epochs"].append(rec)
+        if log:
+            log(f"train: {rec}")
+    hist["steps"] = steps
+    hist["seconds"] = time.perf_counter() - t0
+    return net, hist
+
+
+def compare(net: nn.Net, problems, iters: int, st: FL.Settings, log=print) -> list:
+    """Plain L-BFGS for `iters` iterations, then the learned variant until it
+    reaches the plain run's final objective (at most 2 iters iterations).
+    Returns one record per problem with both wall-clock times."""
+    out = []
+    for name, prob, obs, e0, s0 in problems:
+        obj = Objective(prob, obs, e0, s0, st)
+        plain = minimise(obj, iters)
+        target = plain.final_f
+        objn = Objective(prob, obs, e0, s0, st)
+        pc = Preconditioner(net)
+        learned = minimise(objn, 2 * iters, proposer=lambda x, g: pc(objn, x, g),
+                           target_f=target)
+        reached = learned.final_f <= target
+        rec = {"problem": name, "plain_seconds": round(plain.seconds, 3),
+               "plain_evaluations": obj.evals, "plain_final_f": target,
+               "plain_final_rel_misfit": plain.log[-1].J / obj.J0,
+               "learned_seconds": round(learned.seconds, 3),
+               "learned_evaluations": objn.evals, "learned_final_f": learned.final_f,
+               "learned_reached_plain_final": bool(reached),
+               "learned_iterations": learned.log[-1].k,
+               "net_steps_accepted": sum(1 for it in learned.log if it.source == "net"),
+               "net_seconds": round(pc.seconds, 3)}
+        if log:
+            log(f"compare: {rec}")
+        out.append(rec)
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--runs", type=int, default=667)
+    ap.add_argument("--iters", type=int, default=30)
+    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--eval", type=int, default=8, help="held-out 128x128 problems")
+    ap.add_argument("--survey", action="store_true", help="also compare on the 512x256 survey")
+    ap.add_argument("--survey-iters", type=int, default=10)
+    ap.add_argument("--save", default=None, help="write the trained parameters (.npy)")
+    args = ap.parse_args(argv)
+    if not torch.cuda.is_available():
+        print("precond: no GPU visible", file=sys.stderr)
+        return 1
+    err = lambda m: print(m, file=sys.stderr, flush=True)
+    st = FL.Settings(tv_weight=1e-3)
+    ds, gstats = generate(args.runs, args.iters, 10000, st, log=err)
+    err(f"generate: {gstats}")
+    net, thist = train(ds, args.epochs, args.batch, args.lr, log=err)
+    if args.save:
+        np.save(args.save, net.state_dict()["params"])
+    del ds
+    torch.cuda.empty_cache()
+    problems = []
+    for k in range(args.eval):
+        cfg, prob, obs, e, s, e0, s0 = tiny_problem(50000 + k, 6.0)
+        problems.append((f"tiny-128x128-seed{50000 + k}", prob, obs, e0, s0))
+    res = compare(net, problems, args.iters, st, log=err)
+    out = {"pairs": gstats["runs"] * args.iters, "generate": gstats,
+           "train": {k: thist[k] for k in ("steps", "seconds", "zero_predictor_val")},
+           "train_last": thist["epochs"][-1] if thist["epochs"] else None, "compare": res}
+    if args.survey:
+        from . import fwi
+        from . import inputs as I
+        cfg = I.config_survey()
+        e, s, e0, s0 = I.model_for(cfg)
+        src, rec = I.geometry(cfg)
+        w = torch.from_numpy(I.wavelets(cfg)).cuda()
+        prob = AG.Problem(fwi.grid_from_config(cfg), src, rec, w)
+        with torch.no_grad():
+            obs = AG.traces(prob, torch.from_numpy(e).cuda(), torch.from_numpy(s).cuda())
+        out["compare_survey"] = compare(net, [(cfg.name, prob, obs, torch.from_numpy(e0).cuda(),
+                                               torch.from_numpy(s0).cuda())],
+                                        args.survey_iters, st, log=err)
+    tot_p = sum(r["plain_seconds"] for r in res)
+    tot_l = sum(r["learned_seconds"] for r in res)
+    out["summary"] = {"plain_seconds": round(tot_p, 3), "learned_seconds": round(tot_l, 3),
+                      "reached": sum(r["learned_reached_plain_final"] for r in res),
+                      "problems": len(res)}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -16,19 +16,23 @@ from paper_2506_20513_amd import inputs as I
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "fwi.h")
+NN_HEADER = os.path.join(ROOT, "include", "fwi_nn.h")
 
 FAKE = 1 << 20        # a non-null, 256-aligned address that is never dereferenced
 
 
-def header_functions():
-    text = open(HEADER).read()
+def header_functions(path=HEADER):
+    text = open(path).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
 
 
-def test_library_exports_every_declared_function():
-    names = header_functions()
-    assert set(names) == set(fwi.EXPORTED), names
+@pytest.mark.parametrize("header", ["fwi.h", "fwi_nn.h"])
+def test_library_exports_every_declared_function(header):
+    from paper_2506_20513_amd import nn
+    names = header_functions(os.path.join(ROOT, "include", header))
+    exported = fwi.EXPORTED if header == "fwi.h" else nn.EXPORTED
+    assert set(names) == set(exported), names
     L = ctypes.CDLL(fwi.LIB_PATH)
     for n in names:
         assert hasattr(L, n), n
@@ -226,3 +230,60 @@ def test_batch_argument_checks():
 
 def fwi_grid_copy(g):
     return fwi.fwi_grid.from_buffer_copy(g)
+
+
+def test_nn_argument_checks():
+    """The CNN entry points reject bad sizes, null pointers and misaligned
+    operands with FWI_NN_EINVAL before launching anything."""
+    from paper_2506_20513_amd import nn
+    L = nn.lib()
+    E = -1
+    A = FAKE
+    # channels must be multiples of 32, operands 16-byte aligned
+    assert L.fwi_nn_conv3x3(A, A, None, A, 1, 8, 8, 16, 32, 1, None) == E
+    assert L.fwi_nn_conv3x3(A, A, None, A, 1, 8, 8, 32, 48, 1, None) == E
+    assert L.fwi_nn_conv3x3(A + 2, A, None, A, 1, 8, 8, 32, 32, 1, None) == E
+    assert L.fwi_nn_conv3x3(A, A + 8, None, A, 1, 8, 8, 32, 32, 1, None) == E
+    assert L.fwi_nn_conv3x3(None, A, None, A, 1, 8, 8, 32, 32, 1, None) == E
+    assert L.fwi_nn_conv3x3(A, A, None, A, 0, 8, 8, 32, 32, 1, None) == E
+    assert L.fwi_nn_conv3x3(A, A, None, A, 1 << 16, 1 << 15, 8, 32, 32, 1, None) == E
+    # weight gradient: workspace size and split count
+    need = L.fwi_nn_wgrad_workspace(32, 64, 4)
+    assert need == (4 * 64 * 9 * 32 + 4 * 64) * 4
+    assert L.fwi_nn_wgrad(A, A, A, A, 1, 8, 8, 32, 64, 4, A, need - 1, None) == E
+    assert L.fwi_nn_wgrad(A, A, A, A, 1, 8, 8, 32, 64, 0, A, need, None) == E
+    assert L.fwi_nn_wgrad(A, A, A, A, 1, 8, 8, 32, 64, 4, None, need, None) == E
+    # pooling needs even sides; upsampling even output sides
+    assert L.fwi_nn_pool2(A, A, 1, 7, 8, 32, None) == E
+    assert L.fwi_nn_pool2_bwd(A, A, 1, 8, 9, 32, None) == E
+    assert L.fwi_nn_up2_add(A, None, A, 1, 8, 5, 32, None) == E
+    assert L.fwi_nn_mse(A, A, A, A, A, 10, 32, 33, None) == E
+    assert L.fwi_nn_mse(A, A, A, A, A, 0, 32, 2, None) == E
+    assert L.fwi_nn_adam(A, A, A, A, None, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == E
+    assert L.fwi_nn_pack4(A, A, A, 1, 8, 8, 3, None) == E
+    assert L.fwi_nn_unpack2(A, A, A, 1, 8, 8, 1, None) == E
+    # empty element-wise calls are no-ops
+    assert L.fwi_nn_add(A, A, A, 0, None) == 0
+    assert L.fwi_nn_relu_bwd(A, A, A, 0, None) == 0
+
+
+def test_nn_parameter_layout():
+    """Every parameter block of the network starts 128-byte aligned in the
+    bf16 copy and the blocks tile the flat buffer without overlap."""
+    from paper_2506_20513_amd import nn
+    end = 0
+    for (_, ci, co, _, _), (wo, bo) in zip(nn.LAYERS, nn.param_offsets()):
+        assert wo >= end and wo % 64 == 0 and bo % 64 == 0
+        assert bo >= wo + co * 9 * ci
+        end = bo + co
+    assert nn.param_count() >= end
+    p = nn.init_params(seed=1, out_scale=0.1)
+    assert p.shape == (nn.param_count(),) and np.isfinite(p).all()
+    wo, _ = nn.param_offsets()[0]
+    w0 = p[wo:wo + 32 * 9 * nn.CPAD].reshape(32, 3, 3, nn.CPAD)
+    assert (w0[..., 4:] == 0).all()           # padded input channels carry nothing
+    wo, _ = nn.param_offsets()[-1]
+    wl = p[wo:wo + 32 * 9 * 32].reshape(32, 3, 3, 32)
+    assert (wl[nn.NOUT:] == 0).all() and (wl[:nn.NOUT] != 0).any()
+    p0 = nn.init_params(seed=1)               # default: starts as the zero predictor
+    assert (p0[wo:wo + 32 * 9 * 32] == 0).all()

@@ -1,0 +1,53 @@
+"""The learned-preconditioner pipeline on the GPU at a small scale: pairs
+from plain L-BFGS runs on seeded 128x128 models, training through the CNN
+kernels, and an inversion that tries the network's step first and falls
+back to L-BFGS.  Checks the structure of the data, that training lowers the
+loss, and that the learned run keeps the plain run's guarantees (monotone
+objective, every accepted step passes the decrease test)."""
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+
+
+def test_pairs_training_and_learned_inversion():
+    import torch
+    from paper_2506_20513_amd import fwi_loop as FL
+    from paper_2506_20513_amd import precond as PC
+    st = FL.Settings(tv_weight=1e-3)
+    ds, stats = PC.generate(2, 4, 10000, st, log=lambda m: print(m, flush=True))
+    print("generate", stats, flush=True)
+    assert ds.planes.shape == (8, 4, 128, 128) and ds.targets.shape == (8, 128, 128, 2)
+    assert torch.isfinite(ds.planes).all() and torch.isfinite(ds.targets).all()
+    # the last pair of a run is one step: its target is that step, nonzero
+    assert float(ds.targets[3].abs().max()) > 0
+    # the first gradient of each run is normalised to unit rms
+    for i in (0, 4):
+        for c in (0, 1):
+            r = float(torch.sqrt(torch.mean((ds.planes[i, c] * ds.scales[i, c]).double() ** 2)))
+            assert abs(r - 1.0) < 1e-4
+    net, hist = PC.train(ds, epochs=20, batch=2, lr=1e-3, val_frac=0.0, warmup=10,
+                         log=lambda m: print(m, flush=True))
+    ids = hist["train_ids"]
+    zero = float((ds.targets[ids].double() ** 2).mean())
+    fit = PC.mean_loss(net, ds, ids, batch=4)
+    print("training pairs: zero predictor", zero, "trained", fit, flush=True)
+    assert fit < 0.5 * zero
+    cfg, prob, obs, _, _, e0, s0 = PC.tiny_problem(50000, 6.0)
+    res = PC.compare(net, [("held-out", prob, obs, e0, s0)], 4, st,
+                     log=lambda m: print(m, flush=True))
+    r = res[0]
+    assert r["learned_evaluations"] >= 1 and r["plain_evaluations"] >= 1
+    # objective monotone in the learned run as well
+    obj = PC.Objective(prob, obs, e0, s0, st)
+    pc = PC.Preconditioner(net)
+    run = PC.minimise(obj, 4, proposer=lambda x, g: pc(obj, x, g))
+    fs = [it.f for it in run.log]
+    assert all(b <= a for a, b in zip(fs, fs[1:]))
+    assert pc.calls >= 1
