@@ -1,8 +1,9 @@
-"""Dual-parameter FWI driver on top of the autograd functions (Sec. 3.3 and
-Sec. 4 of arXiv 2506.20513: inversion of eps_r and sigma by gradient-based
-optimisation of the trace misfit, with multiscale inversion, total-variation
-regularisation, zeroed gradients near the surface and clamping to physical
-ranges).
+"""Dual-parameter FWI driver on top of the autograd functions (arXiv
+2506.20513: the inversion loop of Sec. 3.1, the misfit Eq. (6) and Adam
+update of Sec. 2.1, and the optimisation strategies of Sec. 3.4 --
+multiscale inversion, total-variation regularisation (smoothed TV, or
+Algorithm 3 through the HIP kernel), staged learning rates, zeroed
+gradients near the surface and clamping to physical ranges).
 
 The unknowns are the interior models (ny x nx); the CPML ring follows them by
 edge replication, as the synthetic inputs do.  Both are optimised in
@@ -76,6 +77,25 @@ class Settings:
     lbfgs_history: int = 10
     adam_lr: tuple = (0.02, 0.02)         # normalised units, (eps, sigma)
     adam_eps_only: int = 0                # first iterations updating eps_r only
+    adam_lr_stage2: tuple | None = None   # learning rates after the eps_r-only stage
+    tv_mode: str = "smooth"               # "smooth": differentiable TV term;
+                                          # "admm": Algorithm 3 term added to the gradient
+    tv_mu: float = 8.0                    # Algorithm 3 fidelity weight
+    tv_lam: float = 2.0                   # Algorithm 3 penalty parameter
+    tv_iters: int = 20
+
+
+def paper_recipe(iters: int = 150, stage1: int = 50) -> Settings:
+    """The schedule of the cross-hole example (Sec. 4.1): Adam, eps_r alone
+    at learning rate 0.2 for the first `stage1` epochs, then eps_r and
+    sigma at 0.1 and 1e-4 (here divided by eps_scale and sig_scale, the
+    optimiser working in normalised units), Algorithm 3 TV, one row of
+    gradient zeroed below the surface, full band."""
+    st = Settings(bands=(None,), iters=iters, optimizer="adam", mask_rows=1, tv_mode="admm")
+    st.adam_lr = (0.2 / st.eps_scale, 0.0)
+    st.adam_eps_only = stage1
+    st.adam_lr_stage2 = (0.1 / st.eps_scale, 1e-4 / st.sig_scale)
+    return st
 
 
 @dataclass
@@ -122,6 +142,17 @@ def invert(prob: AG.Problem, wavelet_full: torch.Tensor, observed_full: torch.Te
 
     res = Result(eps_r=eps0, sigma=sig0)
     t_start = time.perf_counter()
+    tv_op = None
+    if st.tv_mode == "admm" and st.tv_weight > 0:
+        from . import tv as TVK
+        tv_op = TVK.TV(2, u.shape[0], u.shape[1], st.tv_mu, st.tv_lam, st.tv_weight, st.tv_iters,
+                       device=u.device)
+    elif st.tv_mode not in ("smooth", "admm"):
+        raise ValueError(f"tv_mode {st.tv_mode!r}")
+    if tv_op is not None and st.optimizer == "lbfgs":
+        # the term is added to the gradient without an objective value to
+        # match, which a line search needs
+        raise ValueError("tv_mode 'admm' needs the adam optimizer")
     for fc in st.bands:
         if fc is None:
             w, obs = wavelet_full, observed_full
@@ -140,8 +171,18 @@ def invert(prob: AG.Problem, wavelet_full: torch.Tensor, observed_full: torch.Te
             J = AG.misfit(prob, e, s, obs)
             if J0[0] is None:
                 J0[0] = float(J.detach())
-            loss = J / J0[0] + st.tv_weight * (total_variation(uu) + total_variation(vv))
+            loss = J / J0[0]
+            if tv_op is None:
+                loss = loss + st.tv_weight * (total_variation(uu) + total_variation(vv))
             loss.backward()
+            if tv_op is not None:
+                # Algorithm 3: its term is added to the gradients of both fields
+                with torch.no_grad():
+                    X = torch.stack([u.detach(), v.detach()]).contiguous()
+                    G = torch.stack([u.grad, v.grad]).contiguous()
+                    tv_op(X, G)
+                    u.grad.copy_(torch.where(keep, torch.zeros_like(G[0]), G[0]))
+                    v.grad.copy_(torch.where(keep, torch.zeros_like(G[1]), G[1]))
             res.evaluations += 1
             res.history.append(Record(float(fc or 0), it[0], float(J.detach()),
                                       float(J.detach()) / J0[0], time.perf_counter() - t_start))
@@ -161,6 +202,9 @@ def invert(prob: AG.Problem, wavelet_full: torch.Tensor, observed_full: torch.Te
             opt = torch.optim.Adam([{"params": [u], "lr": st.adam_lr[0]},
                                     {"params": [v], "lr": st.adam_lr[1]}])
             for k in range(st.iters):
+                if k == st.adam_eps_only and st.adam_lr_stage2 is not None:
+                    for grp, lr in zip(opt.param_groups, st.adam_lr_stage2):
+                        grp["lr"] = lr
                 opt.zero_grad()
                 closure()
                 if k < st.adam_eps_only:
@@ -191,6 +235,9 @@ def main(argv=None):
     ap.add_argument("--optimizer", default="lbfgs", choices=["lbfgs", "adam"])
     ap.add_argument("--tv", type=float, default=1e-3)
     ap.add_argument("--nshots", type=int, default=None)
+    ap.add_argument("--tv-mode", default="smooth", choices=["smooth", "admm"])
+    ap.add_argument("--recipe", default=None, choices=["paper"],
+                    help="the paper's Adam schedule with Algorithm 3 TV (overrides the rest)")
     args = ap.parse_args(argv)
     if not torch.cuda.is_available():
         print("fwi_loop: no GPU visible", file=sys.stderr)
@@ -207,7 +254,13 @@ def main(argv=None):
         obs = AG.traces(prob, torch.from_numpy(e).cuda(), torch.from_numpy(s).cuda())
     torch.cuda.synchronize()
     bands = tuple(None if b in ("full", "none") else float(b) for b in args.bands.split(","))
-    st = Settings(bands=bands, iters=args.iters, optimizer=args.optimizer, tv_weight=args.tv)
+    if args.recipe == "paper":
+        st = paper_recipe(iters=args.iters, stage1=max(1, args.iters // 3))
+        st.tv_weight = args.tv
+        bands = st.bands
+    else:
+        st = Settings(bands=bands, iters=args.iters, optimizer=args.optimizer, tv_weight=args.tv,
+                      tv_mode=args.tv_mode)
     et, stt = torch.from_numpy(e).cuda(), torch.from_numpy(s).cuda()
     r = invert(prob, w, obs, torch.from_numpy(e0).cuda(), torch.from_numpy(s0).cuda(), st, cfg.dt,
                log=lambda m: print(m, file=sys.stderr, flush=True))
@@ -217,7 +270,8 @@ def main(argv=None):
         return float(torch.linalg.norm(a[sl] - b[sl]) / torch.linalg.norm(b[sl]))
 
     out = {"workload": cfg.name, "bands_Hz": [b or 0 for b in bands], "iters_per_band": args.iters,
-           "optimizer": args.optimizer, "tv_weight": args.tv, "evaluations": r.evaluations,
+           "optimizer": st.optimizer, "tv_mode": st.tv_mode, "recipe": args.recipe,
+           "tv_weight": args.tv, "evaluations": r.evaluations,
            "seconds": round(r.seconds, 2),
            "seconds_per_evaluation": round(r.seconds / max(1, r.evaluations), 4),
            "final_relative_misfit_last_band": r.history[-1].rel_misfit,

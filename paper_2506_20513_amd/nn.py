@@ -451,3 +451,84 @@ class Net:
         fills dy [N][H][W][32] and self.loss (device double)."""
         mse(y, target, dy, self.loss, self.partials, N * H * W, 32, NOUT)
         return self.loss
+
+
+# ---------------------------------------------------------------------------
+# Throughput measurement
+# ---------------------------------------------------------------------------
+def conv_flops(N: int, H: int, W: int, training: bool) -> float:
+    """Algorithmic FLOPs (2 per multiply-add) of the convolutions of one
+    forward pass, or of a training step: forward, weight gradient and input
+    gradient (none for the first layer)."""
+    tot = 0.0
+    for k, (_, ci, co, lv, _) in enumerate(LAYERS):
+        f = 2.0 * N * (H >> lv) * (W >> lv) * 9 * ci * co
+        tot += f * ((3 if k else 2) if training else 1)
+    return tot
+
+
+def main(argv=None):
+    import argparse
+    import json
+    import sys
+    ap = argparse.ArgumentParser(description="throughput of the preconditioner network kernels")
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--size", default="128x128", help="training image HxW")
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--infer", default="1024x2048", help="inference image HxW (batch 1)")
+    ap.add_argument("--infer-reps", type=int, default=10)
+    args = ap.parse_args(argv)
+    if not torch.cuda.is_available():
+        print("nn: no GPU visible", file=sys.stderr)
+        return 1
+    H, W = (int(v) for v in args.size.split("x"))
+    N = args.batch
+    g = torch.Generator(device="cuda").manual_seed(0)
+    planes = torch.randn(N, 4, H, W, generator=g, device="cuda")
+    tgt = torch.randn(N, H, W, NOUT, generator=g, device="cuda") * 0.1
+    sc = torch.ones(N, 4, device="cuda")
+    net = Net(seed=0, out_scale=0.1)
+    x = torch.empty(N * H * W * CPAD, dtype=BF, device="cuda")
+    dy = torch.empty(N * H * W * CPAD, dtype=BF, device="cuda")
+
+    def step():
+        pack4(planes, sc, x, N, H, W)
+        y = net.forward(x, N, H, W)
+        net.loss_and_grad(y, tgt, dy, N, H, W)
+        net.backward(dy)
+        net.adam_step(1e-4)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    out = {"train": {"batch": N, "image": [H, W], "ms_per_step": round(ms, 4),
+                     "TFLOPs": round(conv_flops(N, H, W, True) / ms * 1e-9, 2)}}
+    Hi, Wi = (int(v) for v in args.infer.split("x"))
+    pl = torch.randn(1, 4, Hi, Wi, generator=g, device="cuda")
+    xi = torch.empty(Hi * Wi * CPAD, dtype=BF, device="cuda")
+    pack4(pl, torch.ones(1, 4, device="cuda"), xi, 1, Hi, Wi)
+    net.forward(xi, 1, Hi, Wi)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.infer_reps):
+        net.forward(xi, 1, Hi, Wi)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.infer_reps
+    out["infer"] = {"image": [Hi, Wi], "ms": round(ms, 4),
+                    "TFLOPs": round(conv_flops(1, Hi, Wi, False) / ms * 1e-9, 2)}
+    out["peak_bf16_TFLOPs"] = 2500.0
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

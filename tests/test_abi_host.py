@@ -27,11 +27,11 @@ def header_functions(path=HEADER):
     return re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
 
 
-@pytest.mark.parametrize("header", ["fwi.h", "fwi_nn.h"])
+@pytest.mark.parametrize("header", ["fwi.h", "fwi_nn.h", "fwi_tv.h"])
 def test_library_exports_every_declared_function(header):
-    from paper_2506_20513_amd import nn
+    from paper_2506_20513_amd import nn, tv
     names = header_functions(os.path.join(ROOT, "include", header))
-    exported = fwi.EXPORTED if header == "fwi.h" else nn.EXPORTED
+    exported = {"fwi.h": fwi.EXPORTED, "fwi_nn.h": nn.EXPORTED, "fwi_tv.h": tv.EXPORTED}[header]
     assert set(names) == set(exported), names
     L = ctypes.CDLL(fwi.LIB_PATH)
     for n in names:
@@ -287,3 +287,26 @@ def test_nn_parameter_layout():
     assert (wl[nn.NOUT:] == 0).all() and (wl[:nn.NOUT] != 0).any()
     p0 = nn.init_params(seed=1)               # default: starts as the zero predictor
     assert (p0[wo:wo + 32 * 9 * 32] == 0).all()
+
+
+def test_tv_argument_checks():
+    """fwi_tv_gradient rejects bad shapes and settings (FWI_EINVAL) and a
+    missing, misaligned or short workspace (FWI_ENOMEM) before launching."""
+    from paper_2506_20513_amd import tv
+    L = tv.lib()
+    f = lambda *v: (ctypes.c_float * len(v))(*v)
+    one = f(1.0, 1.0)
+    need = L.fwi_tv_workspace_bytes(2, 16, 24)
+    assert need >= 6 * 2 * 16 * 24 * 4
+    assert L.fwi_tv_workspace_bytes(0, 16, 24) == 0 and L.fwi_tv_workspace_bytes(5, 16, 24) == 0
+    assert L.fwi_tv_workspace_bytes(1, 1, 24) == 0
+    A = FAKE
+    assert L.fwi_tv_gradient(A, A, 2, 16, 24, one, one, one, 0, A, need, None) == -1
+    assert L.fwi_tv_gradient(None, A, 2, 16, 24, one, one, one, 3, A, need, None) == -1
+    assert L.fwi_tv_gradient(A, A, 2, 16, 24, f(1.0, 0.0), one, one, 3, A, need, None) == -1
+    assert L.fwi_tv_gradient(A, A, 2, 16, 24, one, f(-1.0, 1.0), one, 3, A, need, None) == -1
+    assert L.fwi_tv_gradient(A, A, 5, 16, 24, one, one, one, 3, A, need, None) == -1
+    assert L.fwi_tv_gradient(A, A, 2, 1, 24, one, one, one, 3, A, need, None) == -1
+    assert L.fwi_tv_gradient(A, A, 2, 16, 24, one, one, one, 3, None, need, None) == -4
+    assert L.fwi_tv_gradient(A, A, 2, 16, 24, one, one, one, 3, A + 64, need, None) == -4
+    assert L.fwi_tv_gradient(A, A, 2, 16, 24, one, one, one, 3, A, need - 1, None) == -4
