@@ -6,8 +6,8 @@
  *
  * The paper itself has no such network: it only mentions machine-learning
  * assisted regularisation as related work (Sec. 1).  The inversion it
- * serves is the dual-parameter FWI of Sec. 3.3 (misfit Eq. (6), gradients
- * Eqs. (12)-(13)).
+ * serves is the dual-parameter FWI loop of Sec. 3.1 (misfit Eq. (6),
+ * gradients Eqs. (12)-(13)).
  *
  * Conventions
  * -----------

@@ -45,7 +45,7 @@ def lowpass(x: torch.Tensor, dt: float, fc: float, order: int = 6, dim: int = -1
 def total_variation(x: torch.Tensor, delta: float = 1e-3) -> torch.Tensor:
     """Isotropic TV, mean over cells of sqrt((Dx x)^2 + (Dy x)^2 + delta^2)
     with forward differences (zero across the last row / column), the
-    smoothed form of the TV term of Sec. 3.3."""
+    smoothed form of the TV term of Sec. 3.4."""
     dx = torch.zeros_like(x)
     dy = torch.zeros_like(x)
     dx[:, :-1] = x[:, 1:] - x[:, :-1]

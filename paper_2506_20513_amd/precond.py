@@ -1,6 +1,6 @@
-"""Learned gradient preconditioner for the dual-parameter FWI (Sec. 3.3 of
-arXiv 2506.20513: eps_r and sigma from the trace misfit Eq. (6) with the
-adjoint gradients Eqs. (12)-(13)).
+"""Learned gradient preconditioner for the dual-parameter FWI of arXiv
+2506.20513 (the inversion loop of Sec. 3.1: eps_r and sigma from the trace
+misfit Eq. (6) with the adjoint gradients Eqs. (12)-(13) of Sec. 2.1).
 
 The paper has no learned component; this module adds one on top of its
 inversion.
@@ -13,9 +13,12 @@ inversion.
 3. Inside an inversion, the network proposes a step at every iterate.  The
    objective decrease judges the proposal: it needs a descent direction and
    at least a tenth of the decrease its slope predicts, within two trial
-   lengths.  Otherwise the plain L-BFGS step is taken.  Both kinds of steps
-   feed the same L-BFGS curvature memory.  After two failed proposals in a
-   row the run continues as plain L-BFGS.
+   lengths (the first one carried over from the previous proposal's
+   quadratic fit, so an accepted proposal usually costs one evaluation).
+   Otherwise the plain L-BFGS step is taken.  Both kinds of steps feed the
+   same L-BFGS curvature memory.  A proposal whose first trial
+   length fails is a strike; after two strikes in a row the run continues as
+   plain L-BFGS.
 
 Network input at iterate k: the two gradient planes divided by the rms of
 the run's first gradient (so the input shows how far the gradient has
@@ -26,7 +29,7 @@ Units: the optimiser works on the interior models normalised as in fwi_loop
 The rows just below the surface stay fixed, and every iterate is projected
 onto eps_r >= eps_min, sigma >= sig_min.
 
-    python -m paper_2506_20513_amd.precond --runs 667 --iters 30 --epochs 8
+    python -m paper_2506_20513_amd.precond --runs 667 --iters 30 --epochs 10 --survey
 """
 from __future__ import annotations
 
@@ -161,35 +164,33 @@ def line_search(obj, x, f, g, d, t0=1.0, trials=8, c1=1e-4, shrink=0.25):
     return None
 
 
-def proposal_search(obj, x, f, g, d, c1=0.1):
-    """Two trial lengths along a proposed direction d: t = 1, then the
-    minimiser of the quadratic through f(x), the slope g.d and f(x + d)
-    (kept within [0.1, 4]).  A length is accepted if it achieves at least
-    the fraction c1 of the decrease the slope predicts, a stricter test than
-    the Armijo condition of the L-BFGS steps.  Returns (x_new, f_new, g_new,
-    t) or None."""
+def proposal_search(obj, x, f, g, d, t0=1.0, c1=0.1):
+    """At most two trial lengths along a proposed direction d.  The first is
+    t0; a length is accepted if it achieves at least the fraction c1 of the
+    decrease the slope g.d predicts (stricter than the Armijo test of the
+    L-BFGS steps).  If t0 fails, the second trial is the minimiser of the
+    quadratic through f(x), the slope and the first trial (within [0.05 t0,
+    0.5 t0]).  Returns (result or None, suggested t0 for the next proposal):
+    the quadratic's minimiser from the last trial, within [0.1, 4]."""
     gd = float(torch.dot(g, d))
     if gd >= 0:
-        return None
-    best = None
-    t = 1.0
+        return None, t0
+    t = t0
+    obj.first_trial_passed = False
     for trial in range(2):
         xn = obj.project(x + t * d)
         dec = float(torch.dot(g, xn - x))
         if dec >= 0:
-            return None
+            return None, t0
         fn, gn = obj(xn)
-        if fn <= f + c1 * dec and (best is None or fn < best[1]):
-            best = (xn, fn, gn, t)
-        if trial == 0:
-            curv = fn - f - gd                 # f(x + t d) ~ f + t gd + t^2 curv
-            if curv <= 0:
-                break                          # still descending at t = 1: keep it
-            ts = min(4.0, max(0.1, -gd / (2.0 * curv)))
-            if best is not None and abs(ts - 1.0) < 0.2:
-                break                          # t = 1 is already near the minimum
-            t = ts
-    return best
+        curv = (fn - f - t * gd) / (t * t)     # f(x + s d) ~ f + s gd + s^2 curv
+        ts = -gd / (2.0 * curv) if curv > 0 else 2.0 * t
+        nxt = min(4.0, max(0.1, ts))
+        if fn <= f + c1 * dec:
+            obj.first_trial_passed = trial == 0
+            return (xn, fn, gn, t), nxt
+        t = min(0.5 * t, max(0.05 * t, ts))
+    return None, nxt
 
 
 @dataclass
@@ -216,12 +217,15 @@ class Run:
 
 def minimise(obj: Objective, iters: int, history: int = 10, first_step: float = 0.05,
              proposer=None, target_f: float | None = None, keep: bool = False,
-             max_strikes: int = 2) -> Run:
+             max_strikes: int = 2, log=None) -> Run:
     """L-BFGS on obj from obj.x0 for `iters` iterations (or until f <=
     target_f).  proposer(x, g) -> direction or None is tried first at every
-    iterate (proposal_search: at most two evaluations); the decrease it
-    achieves decides, otherwise the L-BFGS step is taken.  After max_strikes
-    proposals in a row fail, the proposer is no longer asked.  keep: retain
+    iterate (proposal_search: at most two evaluations, starting from the
+    length the previous proposal's quadratic fit suggested); the decrease it
+    achieves decides, otherwise the L-BFGS step is taken.  A proposal whose
+    first trial length does not pass is a strike (even if the second one
+    does); after max_strikes strikes in a row the proposer is no longer
+    asked and the run continues as plain L-BFGS.  keep: retain
     iterates and gradients (for training pairs)."""
     torch.cuda.synchronize() if obj.x0.is_cuda else None
     t0 = time.perf_counter()
@@ -234,21 +238,30 @@ def minimise(obj: Objective, iters: int, history: int = 10, first_step: float = 
         if obj.x0.is_cuda:
             torch.cuda.synchronize()
         run.log.append(Iterate(k, f, obj.last_J, obj.evals, time.perf_counter() - t0, src))
+        if log:
+            it = run.log[-1]
+            log(f"  iterate {it.k}: f {it.f:.6g}, {it.evals} evaluations, {it.seconds:.2f} s, {src}")
         if keep:
             run.xs.append(x.clone())
             run.gs.append(g.clone())
 
     note(0, "start")
     strikes = 0
+    t_net = 1.0
     for k in range(1, iters + 1):
         if target_f is not None and f <= target_f:
             break
         res, src = None, None
         if proposer is not None and strikes < max_strikes:
             d = proposer(x, g)
-            res = proposal_search(obj, x, f, g, d) if d is not None else None
+            passed = False
+            if d is not None:
+                res, t_net = proposal_search(obj, x, f, g, d, t0=t_net)
+                passed = getattr(obj, "first_trial_passed", False)
             src = "net"
-            strikes = 0 if res is not None else strikes + 1
+            # a proposal that needed its second trial length (or failed) costs
+            # more evaluations than an L-BFGS step usually does: a strike
+            strikes = 0 if passed else strikes + 1
         if res is None:
             d = mem.direction(g)
             src = "lbfgs"
@@ -349,7 +362,7 @@ def tiny_problem(seed: int, smoothing: float, device="cuda"):
     e, s = I.model_tiny(cfg, seed)
     e0, s0 = I.smooth_model(e, s, cfg.npml, smoothing)
     src, rec = I.geometry(cfg)
-    w = torch.from_numpy(I.wavelets(cfg)).to(device)
+    w = torch.from_numpy(I.wavelets(cfg).copy()).to(device)
     prob = AG.Problem(fwi.grid_from_config(cfg), src, rec, w, device=device)
     T = lambda a: torch.from_numpy(a).to(device)
     with torch.no_grad():
@@ -455,19 +468,25 @@ def train(ds: Dataset, epochs: int, batch: int = 32, lr: float = 1e-3, seed: int
     return net, hist
 
 
-def compare(net: nn.Net, problems, iters: int, st: FL.Settings, log=print) -> list:
+def compare(net: nn.Net, problems, iters: int, st: FL.Settings, log=print,
+            verbose: bool = False) -> list:
     """Plain L-BFGS for `iters` iterations, then the learned variant until it
     reaches the plain run's final objective (at most 2 iters iterations).
-    Returns one record per problem with both wall-clock times."""
+    Returns one record per problem with both wall-clock times.  verbose:
+    log every iterate."""
     out = []
     for name, prob, obs, e0, s0 in problems:
         obj = Objective(prob, obs, e0, s0, st)
-        plain = minimise(obj, iters)
+        if verbose and log:
+            log(f"{name}: plain L-BFGS")
+        plain = minimise(obj, iters, log=log if verbose else None)
         target = plain.final_f
         objn = Objective(prob, obs, e0, s0, st)
         pc = Preconditioner(net)
+        if verbose and log:
+            log(f"{name}: learned, until f <= {target:.6g}")
         learned = minimise(objn, 2 * iters, proposer=lambda x, g: pc(objn, x, g),
-                           target_f=target)
+                           target_f=target, log=log if verbose else None)
         reached = learned.final_f <= target
         rec = {"problem": name, "plain_seconds": round(plain.seconds, 3),
                "plain_evaluations": obj.evals, "plain_final_f": target,
@@ -484,56 +503,81 @@ def compare(net: nn.Net, problems, iters: int, st: FL.Settings, log=print) -> li
     return out
 
 
+def _survey_problem(cfg):
+    from . import fwi
+    from . import inputs as I
+    e, s, e0, s0 = I.model_for(cfg)
+    src, rec = I.geometry(cfg)
+    w = torch.from_numpy(I.wavelets(cfg).copy()).cuda()
+    prob = AG.Problem(fwi.grid_from_config(cfg), src, rec, w)
+    with torch.no_grad():
+        obs = AG.traces(prob, torch.from_numpy(e).cuda(), torch.from_numpy(s).cuda())
+    return (cfg.name, prob, obs, torch.from_numpy(e0).cuda(), torch.from_numpy(s0).cuda())
+
+
+def _summary(res):
+    return {"plain_seconds": round(sum(r["plain_seconds"] for r in res), 3),
+            "learned_seconds": round(sum(r["learned_seconds"] for r in res), 3),
+            "plain_evaluations": sum(r["plain_evaluations"] for r in res),
+            "learned_evaluations": sum(r["learned_evaluations"] for r in res),
+            "reached": sum(r["learned_reached_plain_final"] for r in res), "problems": len(res)}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--runs", type=int, default=667)
     ap.add_argument("--iters", type=int, default=30)
-    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--epochs", type=int, default=10)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--eval", type=int, default=8, help="held-out 128x128 problems")
     ap.add_argument("--survey", action="store_true", help="also compare on the 512x256 survey")
     ap.add_argument("--survey-iters", type=int, default=10)
+    ap.add_argument("--large", action="store_true", help="also compare on the 2048x1024 model")
+    ap.add_argument("--large-iters", type=int, default=5)
     ap.add_argument("--save", default=None, help="write the trained parameters (.npy)")
+    ap.add_argument("--load", default=None,
+                    help="trained parameters (.npy) to use instead of generating and training")
     args = ap.parse_args(argv)
     if not torch.cuda.is_available():
         print("precond: no GPU visible", file=sys.stderr)
         return 1
     err = lambda m: print(m, file=sys.stderr, flush=True)
     st = FL.Settings(tv_weight=1e-3)
-    ds, gstats = generate(args.runs, args.iters, 10000, st, log=err)
-    err(f"generate: {gstats}")
-    net, thist = train(ds, args.epochs, args.batch, args.lr, log=err)
-    if args.save:
-        np.save(args.save, net.state_dict()["params"])
-    del ds
-    torch.cuda.empty_cache()
+    out = {}
+    if args.load:
+        net = nn.Net(np.load(args.load, allow_pickle=False))
+        out["params"] = args.load
+    else:
+        ds, gstats = generate(args.runs, args.iters, 10000, st, log=err)
+        err(f"generate: {gstats}")
+        net, thist = train(ds, args.epochs, args.batch, args.lr, log=err)
+        if args.save:
+            np.save(args.save, net.state_dict()["params"])
+        out.update({"pairs": gstats["runs"] * args.iters, "generate": gstats,
+                    "train": {k: thist[k] for k in ("steps", "seconds", "zero_predictor_val")},
+                    "train_last": thist["epochs"][-1] if thist["epochs"] else None})
+        del ds
+        torch.cuda.empty_cache()
     problems = []
     for k in range(args.eval):
         cfg, prob, obs, e, s, e0, s0 = tiny_problem(50000 + k, 6.0)
         problems.append((f"tiny-128x128-seed{50000 + k}", prob, obs, e0, s0))
     res = compare(net, problems, args.iters, st, log=err)
-    out = {"pairs": gstats["runs"] * args.iters, "generate": gstats,
-           "train": {k: thist[k] for k in ("steps", "seconds", "zero_predictor_val")},
-           "train_last": thist["epochs"][-1] if thist["epochs"] else None, "compare": res}
+    out["compare"] = res
+    out["summary"] = _summary(res)
+    del problems
+    from . import inputs as I
     if args.survey:
-        from . import fwi
-        from . import inputs as I
-        cfg = I.config_survey()
-        e, s, e0, s0 = I.model_for(cfg)
-        src, rec = I.geometry(cfg)
-        w = torch.from_numpy(I.wavelets(cfg)).cuda()
-        prob = AG.Problem(fwi.grid_from_config(cfg), src, rec, w)
-        with torch.no_grad():
-            obs = AG.traces(prob, torch.from_numpy(e).cuda(), torch.from_numpy(s).cuda())
-        out["compare_survey"] = compare(net, [(cfg.name, prob, obs, torch.from_numpy(e0).cuda(),
-                                               torch.from_numpy(s0).cuda())],
-                                        args.survey_iters, st, log=err)
-    tot_p = sum(r["plain_seconds"] for r in res)
-    tot_l = sum(r["learned_seconds"] for r in res)
-    out["summary"] = {"plain_seconds": round(tot_p, 3), "learned_seconds": round(tot_l, 3),
-                      "reached": sum(r["learned_reached_plain_final"] for r in res),
-                      "problems": len(res)}
+        r = compare(net, [_survey_problem(I.config_survey())], args.survey_iters, st, log=err,
+                    verbose=True)
+        out["compare_survey"] = r
+    if args.large:
+        torch.cuda.empty_cache()
+        err("large: building the problem (observed traces)")
+        r = compare(net, [_survey_problem(I.config_large())], args.large_iters, st, log=err,
+                    verbose=True)
+        out["compare_large"] = r
     print(json.dumps(out), flush=True)
     return 0
 
