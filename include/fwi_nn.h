@@ -43,7 +43,7 @@ extern "C" {
 
 /* y = act(conv3x3(x, w) + bias), act = ReLU if relu != 0 else identity.
  * x [N][H][W][Ci], y [N][H][W][Co] bf16 (must not alias x); w [Co][3][3][Ci]
- * bf16; bias [Co] float32 or NULL.  Ci, Co multiples of 32; N * H < 2^30.
+ * bf16; bias [Co] float32 or NULL.  Ci, Co multiples of 32; N * H * W < 2^36.
  * The input gradient of a convolution is fwi_nn_conv3x3 applied to the
  * output gradient with the weights from fwi_nn_flip (Ci and Co swapped). */
 int fwi_nn_conv3x3(const void *x, const void *w, const float *bias, void *y, int32_t N,
@@ -57,7 +57,8 @@ int fwi_nn_flip(const void *w, void *wf, int32_t Ci, int32_t Co, void *stream);
  *   dw[co][ky][kx][ci] = sum over pixels p of dz[p][co] x[p + (ky-1, kx-1)][ci],
  *   db[co] = sum_p dz[p][co]   (float32 outputs, overwritten).
  * The pixel sum is split over nsplit partial sums reduced in a fixed order,
- * so results are deterministic.  ws: device scratch of at least
+ * so results are deterministic.  x and dz 16-byte aligned, N * H * W < 2^36,
+ * 1 <= nsplit <= 65535.  ws: device scratch of at least
  * fwi_nn_wgrad_workspace(Ci, Co, nsplit) bytes, 4-byte aligned. */
 size_t fwi_nn_wgrad_workspace(int32_t Ci, int32_t Co, int32_t nsplit);
 int fwi_nn_wgrad(const void *x, const void *dz, float *dw, float *db, int32_t N, int32_t H,

@@ -25,45 +25,67 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
 }
 
 // ---------------------------------------------------------------------------
-// y = act(conv3x3(x, w) + bias) as an implicit GEMM: rows are output pixels,
-// columns output channels, the reduction runs over (ky, kx, ci).  A block of
-// four waves covers 64 pixels of one image row; wave w its 16 pixels times
-// 16*NT output channels (NT tiles of 16).
-template <int NT>
+// y = act(conv3x3(x, w) + bias) as an implicit GEMM: rows are output pixels
+// in flattened (n, y, x) order, columns output channels, the reduction runs
+// over (ky, kx, ci).  Tiling over flattened pixels keeps every lane busy on
+// images narrower than a tile.  A block of four waves covers 64 * MT
+// consecutive pixels; wave w owns MT tiles of 16 pixels times 16 * NT output
+// channels, so each weight fragment feeds MT matrix instructions.  A tap at
+// (ky, kx) reads pixel p + (ky - 1) W + (kx - 1) when it lies in the image.
+template <int NT, int MT>
 __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ x,
                                                  const bf16 *__restrict__ w,
                                                  const float *__restrict__ bias,
                                                  bf16 *__restrict__ y, int N, int H, int W,
                                                  int Ci, int Co, int relu) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int xblocks = (W + 63) / 64;
-    int b = blockIdx.x;
-    const int xb = b % xblocks;
-    b /= xblocks;
-    const int row = b % H, n = b / H;
+    const int64_t P = (int64_t)N * H * W;
+    const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * (16 * MT);
     const int co0 = blockIdx.y * (16 * NT);
-    const int px = xb * 64 + wave * 16 + (lane & 15);
     const int kq = (lane >> 4) * 8;
-    f32x4 acc[NT];
+    int py[MT], px[MT];
+    int64_t pp[MT];
+    bool pv[MT];
 #pragma unroll
-    for (int j = 0; j < NT; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int m = 0; m < MT; ++m) {
+        const int64_t p = base + m * 16 + (lane & 15);
+        pv[m] = p < P;
+        pp[m] = pv[m] ? p : 0;
+        px[m] = (int)(pp[m] % W);
+        py[m] = (int)((pp[m] / W) % H);
+    }
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bf16x8 zero{};
     for (int ky = 0; ky < 3; ++ky) {
-        const int yy = row + ky - 1;
         for (int kx = 0; kx < 3; ++kx) {
-            const int xx = px + kx - 1;
-            const bool ok = yy >= 0 && yy < H && xx >= 0 && xx < W && px < W;
-            // out-of-image taps read a valid address and are zeroed
-            const bf16 *xp = x + (ok ? (((size_t)n * H + yy) * W + xx) * Ci : 0) + kq;
+            const int64_t shift = (int64_t)(ky - 1) * W + (kx - 1);
+            const bf16 *xp[MT];
+            bool ok[MT];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                const int yy = py[m] + ky - 1, xx = px[m] + kx - 1;
+                ok[m] = pv[m] && yy >= 0 && yy < H && xx >= 0 && xx < W;
+                // out-of-image taps read a valid address and are zeroed
+                xp[m] = x + (ok[m] ? (pp[m] + shift) * Ci : 0) + kq;
+            }
             const bf16 *wp = w + ((size_t)(co0 + (lane & 15)) * 9 + ky * 3 + kx) * Ci + kq;
             for (int c0 = 0; c0 < Ci; c0 += 32) {
-                bf16x8 a = *reinterpret_cast<const bf16x8 *>(xp + c0);
-                if (!ok) a = zero;
+                bf16x8 a[MT];
+#pragma unroll
+                for (int m = 0; m < MT; ++m) {
+                    a[m] = *reinterpret_cast<const bf16x8 *>(xp[m] + c0);
+                    if (!ok[m]) a[m] = zero;
+                }
 #pragma unroll
                 for (int j = 0; j < NT; ++j) {
                     const bf16x8 bv =
                         *reinterpret_cast<const bf16x8 *>(wp + (size_t)j * 16 * 9 * Ci + c0);
-                    acc[j] = mfma(a, bv, acc[j]);
+#pragma unroll
+                    for (int m = 0; m < MT; ++m) acc[m][j] = mfma(a[m], bv, acc[m][j]);
                 }
             }
         }
@@ -73,12 +95,15 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ x,
         const int co = co0 + 16 * j + (lane & 15);
         const float bb = bias ? bias[co] : 0.f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int pxo = xb * 64 + wave * 16 + 4 * (lane >> 4) + r;
-            if (pxo < W) {
-                float v = acc[j][r] + bb;
-                if (relu) v = fmaxf(v, 0.f);
-                y[(((size_t)n * H + row) * W + pxo) * Co + co] = (bf16)v;
+        for (int m = 0; m < MT; ++m) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t po = base + m * 16 + 4 * (lane >> 4) + r;
+                if (po < P) {
+                    float v = acc[m][j][r] + bb;
+                    if (relu) v = fmaxf(v, 0.f);
+                    y[po * Co + co] = (bf16)v;
+                }
             }
         }
     }
@@ -97,9 +122,11 @@ __global__ void k_flip(const bf16 *__restrict__ w, bf16 *__restrict__ wf, int Ci
 // ---------------------------------------------------------------------------
 // Weight and bias gradients: dw[co][ky][kx][ci] = sum_p dz[p][co] x[p + (ky-1, kx-1)][ci],
 // db[co] = sum_p dz[p][co].  GEMM with the pixels as reduction: a block owns
-// a 32 (co) x 32 (ci) tile of one tap, loops over every gridDim.x-th chunk
-// of 32 pixels and writes its partial sums to part[blockIdx.x]; each chunk's
-// tiles go through LDS transposed so the pixels are contiguous per channel.
+// a 32 (co) x 32 (ci) tile for all nine taps, loops over every gridDim.x-th
+// chunk of 32 pixels and writes its partial sums to part[blockIdx.x].  Each
+// chunk's dz tile and its nine tap-shifted x tiles go through LDS transposed
+// (pixels contiguous per channel); every wave then issues nine matrix
+// instructions per chunk, one per tap, on its 16 x 16 sub-tile.
 constexpr int kPitch = 40;   // LDS row: 32 pixels + 8 padding (80 bytes, 16-byte aligned)
 
 __global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ x,
@@ -107,50 +134,59 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ x,
                                                float *__restrict__ part,
                                                float *__restrict__ bpart, int N, int H, int W,
                                                int Ci, int Co) {
-    __shared__ __attribute__((aligned(16))) bf16 zt[32][kPitch];   // [co][px]
-    __shared__ __attribute__((aligned(16))) bf16 xt[32][kPitch];   // [ci][px]
+    __shared__ __attribute__((aligned(16))) bf16 zt[32][kPitch];      // [co][px]
+    __shared__ __attribute__((aligned(16))) bf16 xt[9][32][kPitch];   // [tap][ci][px]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = threadIdx.x;
     const int nci = Ci / 32;
-    int g = blockIdx.y;
-    const int cit = g % nci;
-    g /= nci;
-    const int tap = g % 9, cot = g / 9;
-    const int ky = tap / 3, kx = tap % 3;
-    const size_t P = (size_t)N * H * W;
-    const size_t nchunk = (P + 31) / 32;
+    const int cit = blockIdx.y % nci, cot = blockIdx.y / nci;
+    const int64_t P = (int64_t)N * H * W;
+    const int64_t nchunk = (P + 31) / 32;
     const int mt = wave >> 1, nt = wave & 1;      // this wave's 16x16 sub-tile
-    f32x4 acc{0.f, 0.f, 0.f, 0.f};
-    float bsum = 0.f;                               // bias partial (tap 0, ci tile 0)
-    const bool do_bias = tap == 0 && cit == 0;
-    // fill role: pixel fp = t >> 3, channels fc .. fc+3
+    f32x4 acc[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;                               // bias partial (ci tile 0)
+    const bool do_bias = cit == 0;
+    // fill role: pixel fp = t >> 3, channels fc .. fc+3 (8 bytes)
     const int fp = t >> 3, fc = (t & 7) * 4;
-    for (size_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
-        const size_t p = ch * 32 + fp;
-        bf16 zv[4] = {(bf16)0.f, (bf16)0.f, (bf16)0.f, (bf16)0.f};
-        bf16 xv[4] = {(bf16)0.f, (bf16)0.f, (bf16)0.f, (bf16)0.f};
+    for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+        const int64_t p = ch * 32 + fp;
+        uint2 zv = make_uint2(0u, 0u);
+        uint2 xv[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) xv[k] = make_uint2(0u, 0u);
         if (p < P) {
-            const bf16 *zp = dz + p * Co + cot * 32 + fc;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) zv[i] = zp[i];
+            zv = *reinterpret_cast<const uint2 *>(dz + p * Co + cot * 32 + fc);
             const int px = (int)(p % W), py = (int)((p / W) % H);
-            const size_t pn = p / ((size_t)W * H);
-            const int xx = px + kx - 1, yy = py + ky - 1;
-            if (xx >= 0 && xx < W && yy >= 0 && yy < H) {
-                const bf16 *xp = x + ((pn * H + yy) * W + xx) * Ci + cit * 32 + fc;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) xv[i] = xp[i];
+            for (int k = 0; k < 9; ++k) {
+                const int xx = px + k % 3 - 1, yy = py + k / 3 - 1;
+                if (xx >= 0 && xx < W && yy >= 0 && yy < H)
+                    xv[k] = *reinterpret_cast<const uint2 *>(
+                        x + (p + (int64_t)(k / 3 - 1) * W + (k % 3 - 1)) * Ci + cit * 32 + fc);
             }
         }
         __syncthreads();   // previous chunk's reads done
+        {
+            const bf16 *zb = reinterpret_cast<const bf16 *>(&zv);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            zt[fc + i][fp] = zv[i];
-            xt[fc + i][fp] = xv[i];
+            for (int i = 0; i < 4; ++i) zt[fc + i][fp] = zb[i];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const bf16 *xb = reinterpret_cast<const bf16 *>(&xv[k]);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) xt[k][fc + i][fp] = xb[i];
+            }
         }
         __syncthreads();
-        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&zt[16 * mt + (lane & 15)][8 * (lane >> 4)]);
-        const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&xt[16 * nt + (lane & 15)][8 * (lane >> 4)]);
-        acc = mfma(a, bv, acc);
+        const bf16x8 a =
+            *reinterpret_cast<const bf16x8 *>(&zt[16 * mt + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const bf16x8 bv =
+                *reinterpret_cast<const bf16x8 *>(&xt[k][16 * nt + (lane & 15)][8 * (lane >> 4)]);
+            acc[k] = mfma(a, bv, acc[k]);
+        }
         if (do_bias && t < 32) {
 #pragma unroll 8
             for (int q = 0; q < 32; ++q) bsum += (float)zt[t][q];
@@ -160,22 +196,36 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ x,
     const size_t tile = (size_t)Co * 9 * Ci;
     float *o = part + blockIdx.x * tile;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int co = cot * 32 + 16 * mt + 4 * (lane >> 4) + r;
-        const int ci = cit * 32 + 16 * nt + (lane & 15);
-        o[((size_t)co * 9 + tap) * Ci + ci] = acc[r];
-    }
+    for (int k = 0; k < 9; ++k)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int co = cot * 32 + 16 * mt + 4 * (lane >> 4) + r;
+            const int ci = cit * 32 + 16 * nt + (lane & 15);
+            o[((size_t)co * 9 + k) * Ci + ci] = acc[k][r];
+        }
     if (do_bias && t < 32) bpart[(size_t)blockIdx.x * Co + cot * 32 + t] = bsum;
 }
 
-// out[i] = sum_k part[k][i] in fixed order k = 0 .. nsplit-1
-__global__ void k_reduce(const float *__restrict__ part, float *__restrict__ out, size_t n,
-                         int nsplit) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float s = 0.f;
-    for (int k = 0; k < nsplit; ++k) s += part[(size_t)k * n + i];
-    out[i] = s;
+// out[i] = sum_k part[k][i]: 64 outputs per block, four groups of waves
+// summing the splits k = g (mod 4) with four accumulators each, combined in
+// a fixed order (deterministic).
+__global__ __launch_bounds__(256) void k_reduce(const float *__restrict__ part,
+                                                float *__restrict__ out, size_t n, int nsplit) {
+    __shared__ float red[4][64];
+    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const size_t i = (size_t)blockIdx.x * 64 + lane;
+    float s[4] = {0.f, 0.f, 0.f, 0.f};
+    if (i < n) {
+        int k = g;
+        for (; k + 12 < nsplit; k += 16) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s[u] += part[(size_t)(k + 4 * u) * n + i];
+        }
+        for (int u = 0; k < nsplit; k += 4, ++u) s[u] += part[(size_t)k * n + i];
+    }
+    red[g][lane] = (s[0] + s[1]) + (s[2] + s[3]);
+    __syncthreads();
+    if (g == 0 && i < n) out[i] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
 }
 
 // ---------------------------------------------------------------------------
@@ -342,17 +392,28 @@ int fwi_nn_conv3x3(const void *x, const void *w, const float *bias, void *y, int
     if (!x || !w || !y || N < 1 || H < 1 || W < 1 || Ci < 32 || Co < 32 || Ci % 32 || Co % 32 ||
         !al16(x) || !al16(w))
         return FWI_NN_EINVAL;
-    if ((int64_t)N * H > (int64_t)1 << 30) return FWI_NN_EINVAL;
+    if ((int64_t)N * H * W >= (int64_t)1 << 36) return FWI_NN_EINVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const unsigned gx = (unsigned)(N * H * ((W + 63) / 64));
+    const int64_t P = (int64_t)N * H * W;
     const bf16 *xb = static_cast<const bf16 *>(x);
     const bf16 *wb = static_cast<const bf16 *>(w);
     bf16 *yb = static_cast<bf16 *>(y);
-    if (Co % 64 == 0)
-        hipLaunchKernelGGL(k_conv3x3<4>, dim3(gx, Co / 64), dim3(256), 0, st, xb, wb, bias, yb, N,
+    const int nt = Co % 64 == 0 ? 4 : 2;
+    const unsigned gy = (unsigned)(Co / (16 * nt));
+    // two 16-pixel tiles per wave when that still gives the chip >= 1024 blocks
+    const bool mt2 = (P + 127) / 128 * gy >= 1024;
+    const unsigned gx = (unsigned)(mt2 ? (P + 127) / 128 : (P + 63) / 64);
+    if (nt == 4 && mt2)
+        hipLaunchKernelGGL((k_conv3x3<4, 2>), dim3(gx, gy), dim3(256), 0, st, xb, wb, bias, yb, N,
+                           H, W, Ci, Co, relu);
+    else if (nt == 4)
+        hipLaunchKernelGGL((k_conv3x3<4, 1>), dim3(gx, gy), dim3(256), 0, st, xb, wb, bias, yb, N,
+                           H, W, Ci, Co, relu);
+    else if (mt2)
+        hipLaunchKernelGGL((k_conv3x3<2, 2>), dim3(gx, gy), dim3(256), 0, st, xb, wb, bias, yb, N,
                            H, W, Ci, Co, relu);
     else
-        hipLaunchKernelGGL(k_conv3x3<2>, dim3(gx, Co / 32), dim3(256), 0, st, xb, wb, bias, yb, N,
+        hipLaunchKernelGGL((k_conv3x3<2, 1>), dim3(gx, gy), dim3(256), 0, st, xb, wb, bias, yb, N,
                            H, W, Ci, Co, relu);
     return status(hipGetLastError());
 }
@@ -373,20 +434,23 @@ int fwi_nn_wgrad(const void *x, const void *dz, float *dw, float *db, int32_t N,
                  int32_t W, int32_t Ci, int32_t Co, int32_t nsplit, void *ws, size_t ws_bytes,
                  void *stream) {
     if (!x || !dz || !dw || !db || !ws || N < 1 || H < 1 || W < 1 || Ci < 32 || Co < 32 ||
-        Ci % 32 || Co % 32 || nsplit < 1 || nsplit > 65535 ||
+        Ci % 32 || Co % 32 || nsplit < 1 || nsplit > 65535 || !al16(x) || !al16(dz) ||
+        (int64_t)N * H * W >= (int64_t)1 << 36 ||
         ws_bytes < fwi_nn_wgrad_workspace(Ci, Co, nsplit))
         return FWI_NN_EINVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
     float *part = static_cast<float *>(ws);
     float *bpart = part + (size_t)nsplit * Co * 9 * Ci;
-    hipLaunchKernelGGL(k_wgrad, dim3(nsplit, (Co / 32) * 9 * (Ci / 32)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_wgrad, dim3(nsplit, (Co / 32) * (Ci / 32)), dim3(256), 0, st,
                        static_cast<const bf16 *>(x), static_cast<const bf16 *>(dz), part, bpart, N,
                        H, W, Ci, Co);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return FWI_NN_EHIP;
     const size_t nw = (size_t)Co * 9 * Ci;
-    hipLaunchKernelGGL(k_reduce, dim3(blocks_for(nw)), dim3(256), 0, st, part, dw, nw, nsplit);
-    hipLaunchKernelGGL(k_reduce, dim3(blocks_for(Co)), dim3(256), 0, st, bpart, db, (size_t)Co,
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((nw + 63) / 64)), dim3(256), 0, st, part, dw, nw,
+                       nsplit);
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((Co + 63) / 64)), dim3(256), 0, st, bpart, db,
+                       (size_t)Co,
                        nsplit);
     return status(hipGetLastError());
 }

@@ -347,8 +347,8 @@ class Net:
         for _, ci, co, lv, _ in LAYERS:
             h, w = hw[lv]
             chunks = (N * h * w + 31) // 32
-            tiles = (co // 32) * 9 * (ci // 32)
-            ns = int(max(1, min(chunks, (4096 + tiles - 1) // tiles, 256)))
+            tiles = (co // 32) * (ci // 32)
+            ns = int(max(1, min(chunks, (2048 + tiles - 1) // tiles, 512)))
             self.nsplit.append(ns)
             wsb = max(wsb, wgrad_workspace(ci, co, ns))
         self.wsg = torch.empty((wsb + 3) // 4, dtype=F32, device=dev)

@@ -56,7 +56,9 @@ def _close_bf16(got, ref, absref, what):
 
 
 @pytest.mark.parametrize("N,H,W,Ci,Co,relu", [(2, 13, 70, 32, 64, 1), (1, 9, 130, 64, 96, 0),
-                                              (3, 5, 17, 96, 32, 1), (1, 1, 1, 32, 32, 0)])
+                                              (3, 5, 17, 96, 32, 1), (1, 1, 1, 32, 32, 0),
+                                              # two 16-pixel tiles per wave, ragged last block
+                                              (8, 61, 67, 32, 256, 1), (16, 61, 67, 32, 96, 0)])
 def test_conv3x3_matches_reference(N, H, W, Ci, Co, relu):
     import torch
     x = _bf((N, H, W, Ci), 1)
