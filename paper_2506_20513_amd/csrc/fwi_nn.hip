@@ -295,6 +295,108 @@ __global__ void k_add(const bf16 *a, const bf16 *b,
     if (i < n) y[i] = (bf16)((float)a[i] + (float)b[i]);
 }
 
+// The same element-wise kernels on 8 channels (16 bytes) per thread, used
+// when the channel count is a multiple of 8 and every operand is 16-byte
+// aligned; each value is computed exactly as in the one-channel kernels.
+__device__ __forceinline__ bf16x8 ld8(const bf16 *p) { return *reinterpret_cast<const bf16x8 *>(p); }
+__device__ __forceinline__ void st8(bf16 *p, bf16x8 v) { *reinterpret_cast<bf16x8 *>(p) = v; }
+
+__global__ void k_relu_bwd8(const bf16 *__restrict__ y, const bf16 *__restrict__ dy,
+                            bf16 *__restrict__ dz, size_t n8) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n8) return;
+    const bf16x8 a = ld8(y + 8 * i), g = ld8(dy + 8 * i);
+    bf16x8 o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = (float)a[k] > 0.f ? g[k] : (bf16)0.f;
+    st8(dz + 8 * i, o);
+}
+
+__global__ void k_add8(const bf16 *a, const bf16 *b, bf16 *y, size_t n8) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n8) return;
+    const bf16x8 u = ld8(a + 8 * i), v = ld8(b + 8 * i);
+    bf16x8 o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = (bf16)((float)u[k] + (float)v[k]);
+    st8(y + 8 * i, o);
+}
+
+__global__ void k_pool8(const bf16 *__restrict__ x, bf16 *__restrict__ y, int N, int H, int W,
+                        int C) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int Ho = H / 2, Wo = W / 2, C8 = C / 8;
+    if (i >= (size_t)N * Ho * Wo * C8) return;
+    const int c = (int)(i % C8) * 8;
+    const size_t r = i / C8;
+    const int xo = (int)(r % Wo), yo = (int)((r / Wo) % Ho);
+    const size_t n = r / ((size_t)Wo * Ho);
+    const bf16 *p = x + ((n * H + 2 * yo) * W + 2 * xo) * C + c;
+    const bf16x8 a = ld8(p), b = ld8(p + C), d = ld8(p + (size_t)W * C), e = ld8(p + (size_t)W * C + C);
+    bf16x8 o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        o[k] = (bf16)(0.25f * ((float)a[k] + (float)b[k] + (float)d[k] + (float)e[k]));
+    st8(y + r * C + c, o);
+}
+
+__global__ void k_pool_bwd8(const bf16 *__restrict__ dy, bf16 *__restrict__ dx, int N, int H,
+                            int W, int C) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int C8 = C / 8;
+    if (i >= (size_t)N * H * W * C8) return;
+    const int c = (int)(i % C8) * 8;
+    const size_t r = i / C8;
+    const int xx = (int)(r % W), yy = (int)((r / W) % H);
+    const size_t n = r / ((size_t)W * H);
+    const bf16x8 g = ld8(dy + ((n * (H / 2) + yy / 2) * (W / 2) + xx / 2) * C + c);
+    bf16x8 o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = (bf16)(0.25f * (float)g[k]);
+    st8(dx + r * C + c, o);
+}
+
+__global__ void k_up_add8(const bf16 *__restrict__ x, const bf16 *__restrict__ s,
+                          bf16 *__restrict__ y, int N, int Ho, int Wo, int C) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int C8 = C / 8;
+    if (i >= (size_t)N * Ho * Wo * C8) return;
+    const int c = (int)(i % C8) * 8;
+    const size_t r = i / C8;
+    const int xx = (int)(r % Wo), yy = (int)((r / Wo) % Ho);
+    const size_t n = r / ((size_t)Wo * Ho);
+    const bf16x8 u = ld8(x + ((n * (Ho / 2) + yy / 2) * (Wo / 2) + xx / 2) * C + c);
+    bf16x8 o;
+    if (s) {
+        const bf16x8 v = ld8(s + r * C + c);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) o[k] = (bf16)((float)u[k] + (float)v[k]);
+    } else {
+        o = u;
+    }
+    st8(y + r * C + c, o);
+}
+
+__global__ void k_up_bwd8(const bf16 *__restrict__ dy, bf16 *__restrict__ dx, int N, int Hi,
+                          int Wi, int C) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int C8 = C / 8;
+    if (i >= (size_t)N * Hi * Wi * C8) return;
+    const int c = (int)(i % C8) * 8;
+    const size_t r = i / C8;
+    const int xx = (int)(r % Wi), yy = (int)((r / Wi) % Hi);
+    const size_t n = r / ((size_t)Wi * Hi);
+    const int W2 = 2 * Wi;
+    const bf16 *p = dy + ((n * 2 * Hi + 2 * yy) * W2 + 2 * xx) * C + c;
+    const bf16x8 a = ld8(p), b = ld8(p + C), d = ld8(p + (size_t)W2 * C),
+                 e = ld8(p + (size_t)W2 * C + C);
+    bf16x8 o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        o[k] = (bf16)((float)a[k] + (float)b[k] + (float)d[k] + (float)e[k]);
+    st8(dx + r * C + c, o);
+}
+
 // Mean squared error over the first `cout` channels of y [P][C] against
 // target [P][cout] (FP32): per-block partial sums (double) and the gradient
 // dy = 2 (y - t) / (P cout) (zero in the other channels).
@@ -325,13 +427,21 @@ __global__ __launch_bounds__(256) void k_mse(const bf16 *__restrict__ y,
     }
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
-__global__ void k_sum(const double *__restrict__ partial, int n, double scale,
-                      double *__restrict__ out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < n; ++i) s += partial[i];
-        *out = s * scale;
+
+// *out = scale * sum of the partials: 64 strided sums, then a fixed-order
+// tree (deterministic)
+__global__ __launch_bounds__(64) void k_sum(const double *__restrict__ partial, int n,
+                                            double scale, double *__restrict__ out) {
+    __shared__ double red[64];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += 64) a += partial[i];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int s = 32; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) *out = red[0] * scale;
 }
 
 // Adam on FP32 masters with a BF16 copy for the kernels (bf16 may be null).
@@ -398,7 +508,9 @@ int fwi_nn_conv3x3(const void *x, const void *w, const float *bias, void *y, int
     const bf16 *xb = static_cast<const bf16 *>(x);
     const bf16 *wb = static_cast<const bf16 *>(w);
     bf16 *yb = static_cast<bf16 *>(y);
-    const int nt = Co % 64 == 0 ? 4 : 2;
+    // 64-channel tiles, unless that leaves the chip with fewer than 1024 blocks
+    int nt = Co % 64 == 0 ? 4 : 2;
+    if (nt == 4 && (P + 63) / 64 * (Co / 64) < 1024) nt = 2;
     const unsigned gy = (unsigned)(Co / (16 * nt));
     // two 16-pixel tiles per wave when that still gives the chip >= 1024 blocks
     const bool mt2 = (P + 127) / 128 * gy >= 1024;
@@ -458,17 +570,28 @@ int fwi_nn_wgrad(const void *x, const void *dz, float *dw, float *db, int32_t N,
 int fwi_nn_relu_bwd(const void *y, const void *dy, void *dz, size_t n, void *stream) {
     if (!y || !dy || !dz) return FWI_NN_EINVAL;
     if (n == 0) return FWI_NN_OK;
-    hipLaunchKernelGGL(k_relu_bwd, dim3(blocks_for(n)), dim3(256), 0,
-                       static_cast<hipStream_t>(stream), static_cast<const bf16 *>(y),
-                       static_cast<const bf16 *>(dy), static_cast<bf16 *>(dz), n);
+    if (n % 8 == 0 && al16(y) && al16(dy) && al16(dz))
+        hipLaunchKernelGGL(k_relu_bwd8, dim3(blocks_for(n / 8)), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), static_cast<const bf16 *>(y),
+                           static_cast<const bf16 *>(dy), static_cast<bf16 *>(dz), n / 8);
+    else
+        hipLaunchKernelGGL(k_relu_bwd, dim3(blocks_for(n)), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), static_cast<const bf16 *>(y),
+                           static_cast<const bf16 *>(dy), static_cast<bf16 *>(dz), n);
     return status(hipGetLastError());
 }
 
 int fwi_nn_pool2(const void *x, void *y, int32_t N, int32_t H, int32_t W, int32_t C, void *stream) {
     if (!x || !y || N < 1 || H < 2 || W < 2 || H % 2 || W % 2 || C < 1) return FWI_NN_EINVAL;
     const size_t n = (size_t)N * (H / 2) * (W / 2) * C;
-    hipLaunchKernelGGL(k_pool, dim3(blocks_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream),
-                       static_cast<const bf16 *>(x), static_cast<bf16 *>(y), N, H, W, C);
+    if (C % 8 == 0 && al16(x) && al16(y))
+        hipLaunchKernelGGL(k_pool8, dim3(blocks_for(n / 8)), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), static_cast<const bf16 *>(x),
+                           static_cast<bf16 *>(y), N, H, W, C);
+    else
+        hipLaunchKernelGGL(k_pool, dim3(blocks_for(n)), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), static_cast<const bf16 *>(x),
+                           static_cast<bf16 *>(y), N, H, W, C);
     return status(hipGetLastError());
 }
 
@@ -476,9 +599,14 @@ int fwi_nn_pool2_bwd(const void *dy, void *dx, int32_t N, int32_t H, int32_t W, 
                      void *stream) {
     if (!dy || !dx || N < 1 || H < 2 || W < 2 || H % 2 || W % 2 || C < 1) return FWI_NN_EINVAL;
     const size_t n = (size_t)N * H * W * C;
-    hipLaunchKernelGGL(k_pool_bwd, dim3(blocks_for(n)), dim3(256), 0,
-                       static_cast<hipStream_t>(stream), static_cast<const bf16 *>(dy),
-                       static_cast<bf16 *>(dx), N, H, W, C);
+    if (C % 8 == 0 && al16(dy) && al16(dx))
+        hipLaunchKernelGGL(k_pool_bwd8, dim3(blocks_for(n / 8)), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), static_cast<const bf16 *>(dy),
+                           static_cast<bf16 *>(dx), N, H, W, C);
+    else
+        hipLaunchKernelGGL(k_pool_bwd, dim3(blocks_for(n)), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), static_cast<const bf16 *>(dy),
+                           static_cast<bf16 *>(dx), N, H, W, C);
     return status(hipGetLastError());
 }
 
@@ -486,9 +614,14 @@ int fwi_nn_up2_add(const void *x, const void *skip, void *y, int32_t N, int32_t 
                    int32_t C, void *stream) {
     if (!x || !y || N < 1 || Ho < 2 || Wo < 2 || Ho % 2 || Wo % 2 || C < 1) return FWI_NN_EINVAL;
     const size_t n = (size_t)N * Ho * Wo * C;
-    hipLaunchKernelGGL(k_up_add, dim3(blocks_for(n)), dim3(256), 0,
-                       static_cast<hipStream_t>(stream), static_cast<const bf16 *>(x),
-                       static_cast<const bf16 *>(skip), static_cast<bf16 *>(y), N, Ho, Wo, C);
+    if (C % 8 == 0 && al16(x) && al16(y) && (!skip || al16(skip)))
+        hipLaunchKernelGGL(k_up_add8, dim3(blocks_for(n / 8)), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), static_cast<const bf16 *>(x),
+                           static_cast<const bf16 *>(skip), static_cast<bf16 *>(y), N, Ho, Wo, C);
+    else
+        hipLaunchKernelGGL(k_up_add, dim3(blocks_for(n)), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), static_cast<const bf16 *>(x),
+                           static_cast<const bf16 *>(skip), static_cast<bf16 *>(y), N, Ho, Wo, C);
     return status(hipGetLastError());
 }
 
@@ -496,18 +629,28 @@ int fwi_nn_up2_bwd(const void *dy, void *dx, int32_t N, int32_t Hi, int32_t Wi, 
                    void *stream) {
     if (!dy || !dx || N < 1 || Hi < 1 || Wi < 1 || C < 1) return FWI_NN_EINVAL;
     const size_t n = (size_t)N * Hi * Wi * C;
-    hipLaunchKernelGGL(k_up_bwd, dim3(blocks_for(n)), dim3(256), 0,
-                       static_cast<hipStream_t>(stream), static_cast<const bf16 *>(dy),
-                       static_cast<bf16 *>(dx), N, Hi, Wi, C);
+    if (C % 8 == 0 && al16(dy) && al16(dx))
+        hipLaunchKernelGGL(k_up_bwd8, dim3(blocks_for(n / 8)), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), static_cast<const bf16 *>(dy),
+                           static_cast<bf16 *>(dx), N, Hi, Wi, C);
+    else
+        hipLaunchKernelGGL(k_up_bwd, dim3(blocks_for(n)), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), static_cast<const bf16 *>(dy),
+                           static_cast<bf16 *>(dx), N, Hi, Wi, C);
     return status(hipGetLastError());
 }
 
 int fwi_nn_add(const void *a, const void *b, void *y, size_t n, void *stream) {
     if (!a || !b || !y) return FWI_NN_EINVAL;
     if (n == 0) return FWI_NN_OK;
-    hipLaunchKernelGGL(k_add, dim3(blocks_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream),
-                       static_cast<const bf16 *>(a), static_cast<const bf16 *>(b),
-                       static_cast<bf16 *>(y), n);
+    if (n % 8 == 0 && al16(a) && al16(b) && al16(y))
+        hipLaunchKernelGGL(k_add8, dim3(blocks_for(n / 8)), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), static_cast<const bf16 *>(a),
+                           static_cast<const bf16 *>(b), static_cast<bf16 *>(y), n / 8);
+    else
+        hipLaunchKernelGGL(k_add, dim3(blocks_for(n)), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), static_cast<const bf16 *>(a),
+                           static_cast<const bf16 *>(b), static_cast<bf16 *>(y), n);
     return status(hipGetLastError());
 }
 

@@ -9,7 +9,9 @@ Two kinds, each written as a short markdown file:
             event average for the same launches;
   counters  HBM bytes per launch from one FETCH_SIZE and one WRITE_SIZE run,
             each scaled by what the same counter reads for the benchmark's
-            plain device copy of known size (`--copy-probe-mb`).
+            plain device copy of known size (`--copy-probe-mb`);
+  stats     per-kernel dispatch statistics of any run (the preconditioner
+            network's kernels, the TV kernel), with the run's JSON line.
 
 The counter summary carries the hash of the stencil kernel sources, so the
 benchmark reports measured traffic only for the kernels that were profiled.
@@ -184,9 +186,45 @@ def read_traffic(path: str, kernel: str, grid, shots: int):
     return None if k is None else float(k["traffic_bytes"])
 
 
+def stats_summary(a) -> str:
+    """Per-kernel dispatch statistics of any run, with the program's own
+    JSON result line (for kernels other than the stencils)."""
+    stats = _csv(a.run_dir, "kernel_stats.csv")
+    tot = sum(float(r["TotalDurationNs"]) for r in stats)
+    src = hashlib.sha256()
+    for rel in a.sources.split(","):
+        with open(os.path.join(HERE, rel), "rb") as f:
+            src.update(f.read())
+    out = [f"# rocprofv3 kernel statistics: {a.title}", "",
+           "Command (from the repository root):", "", "```", a.command, "```", "",
+           f"Kernel sources ({a.sources}) hash: `{src.hexdigest()[:16]}`", "",
+           "| kernel | calls | avg us | min us | max us | total ms | % |",
+           "|---|---:|---:|---:|---:|---:|---:|"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:a.top]:
+        name = r["Name"].replace("(anonymous namespace)::", "").replace("|", "/")[:80]
+        out.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                   f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                   f"{float(r['TotalDurationNs']) / 1e6:.3f} | "
+                   f"{100.0 * float(r['TotalDurationNs']) / tot:.1f} |")
+    if a.result_json:
+        out += ["", "Result line of the profiled run:", "", "```json",
+                json.dumps(_bench_line(a.result_json)), "```"]
+    out.append("")
+    return "\n".join(out)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="kind", required=True)
+    k = sub.add_parser("stats")
+    k.add_argument("--run-dir", required=True)
+    k.add_argument("--title", required=True)
+    k.add_argument("--command", required=True)
+    k.add_argument("--sources", required=True,
+                   help="comma-separated kernel sources relative to the package")
+    k.add_argument("--result-json", default=None)
+    k.add_argument("--top", type=int, default=16)
+    k.add_argument("--out", required=True)
     t = sub.add_parser("trace")
     t.add_argument("--run-dir", required=True)
     t.add_argument("--bench-json", required=True)
@@ -198,7 +236,8 @@ def main(argv=None):
         c.add_argument("--" + x, required=True)
     c.add_argument("--copy-mb", type=int, required=True)
     a = ap.parse_args(argv)
-    text = trace_summary(a) if a.kind == "trace" else counters_summary(a)
+    text = {"trace": trace_summary, "counters": counters_summary,
+            "stats": stats_summary}[a.kind](a)
     with open(a.out, "w") as f:
         f.write(text)
     print(text)

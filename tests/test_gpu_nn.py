@@ -113,10 +113,11 @@ def test_weight_gradient_matches_reference(nsplit):
     assert float((db.double().cpu() - dbr).abs().max()) <= 1e-5 * float(g.double().abs().sum(dim=(0, 1, 2)).max())
 
 
-def test_elementwise_kernels_match_reference():
+@pytest.mark.parametrize("C", [32, 4])   # 8-channel vector kernels, and the scalar ones
+def test_elementwise_kernels_match_reference(C):
     import torch
     import torch.nn.functional as F
-    N, H, W, C = 2, 6, 10, 32
+    N, H, W = 2, 6, 10
     x = _bf((N, H, W, C), 10)
     s = _bf((N, H, W, C), 11)
     dev = lambda t: _dev(t)
@@ -148,6 +149,16 @@ def test_elementwise_kernels_match_reference():
              (u0, R.nhwc(F.interpolate(R.nchw(q.double()), scale_factor=2, mode="nearest")), "up"),
              (du, ref_du, "up adjoint"), (dz, ref_dz, "relu backward"),
              (a, x.double() + s.double(), "add")]
+    # misaligned operands (2-byte offset) take the scalar kernels
+    n = x.numel() - 1
+    xs, ss = dev(x).view(-1)[1:], dev(s).view(-1)[1:]
+    dz2 = torch.empty(n + 1, dtype=torch.bfloat16, device="cuda")[1:]
+    a2 = torch.empty(n + 1, dtype=torch.bfloat16, device="cuda")[1:]
+    nn.relu_bwd(xs, ss, dz2, n)
+    nn.add(xs, ss, a2, n)
+    torch.cuda.synchronize()
+    cases += [(dz2, ref_dz.reshape(-1)[1:], "relu backward, misaligned"),
+              (a2, (x.double() + s.double()).reshape(-1)[1:], "add, misaligned")]
     for got, r, what in cases:
         got = got.double().cpu().reshape(r.shape)
         # one rounding to bf16 of a value computed exactly (or within float32)
