@@ -28,9 +28,10 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
 // y = act(conv3x3(x, w) + bias) as an implicit GEMM: rows are output pixels
 // in flattened (n, y, x) order, columns output channels, the reduction runs
 // over (ky, kx, ci).  Tiling over flattened pixels keeps every lane busy on
-// images narrower than a tile.  A block of four waves covers 64 * MT
-// consecutive pixels; wave w owns MT tiles of 16 pixels times 16 * NT output
-// channels, so each weight fragment feeds MT matrix instructions.  A tap at
+// images narrower than a tile.  This form, with operands read straight from
+// global memory, serves layers too small for the LDS-tiled kernel below: a
+// block of four waves covers 64 * MT consecutive pixels; wave w owns MT
+// tiles of 16 pixels times 16 * NT output channels.  A tap at
 // (ky, kx) reads pixel p + (ky - 1) W + (kx - 1) when it lies in the image.
 template <int NT, int MT>
 __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ x,
@@ -101,6 +102,118 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ x,
                 const int64_t po = base + m * 16 + 4 * (lane >> 4) + r;
                 if (po < P) {
                     float v = acc[m][j][r] + bb;
+                    if (relu) v = fmaxf(v, 0.f);
+                    y[po * Co + co] = (bf16)v;
+                }
+            }
+        }
+    }
+}
+
+// The same convolution with both operand tiles staged in LDS: a block
+// computes 128 consecutive (flattened) pixels x BN output channels.  Each
+// reduction step (one tap, 32 input channels) copies the 128 x 32 input tile
+// (zeros outside the image) and the BN x 32 weight tile into one of two LDS
+// buffers; the global loads of step k+1 are issued before the matrix
+// instructions of step k, and one barrier per step separates the buffers.
+// Wave w computes pixels [32 w, 32 w + 32) x all BN channels: 2 x BN/16
+// MFMAs per step from LDS fragments.
+constexpr int kTP = 40;      // LDS row pitch in bf16: 32 channels + 8 padding (80 bytes)
+
+struct Stage {
+    uint4 a0, a1, b;             // 16 input channels (two pieces) and 8 weight channels
+};
+
+// global loads of reduction step k for one thread's copy roles
+__device__ __forceinline__ Stage conv_gload(const bf16 *__restrict__ x, const bf16 *__restrict__ w,
+                                            int k, int nck, int Ci, int H, int W, bool pvA,
+                                            int64_t ppA, int pyA, int pxA, int ah, bool bact,
+                                            int co0, int bco, int bq) {
+    Stage s;
+    const int tap = k / nck, c0 = (k - tap * nck) * 32;
+    const int ky = tap / 3, kx = tap - ky * 3;
+    const int yy = pyA + ky - 1, xx = pxA + kx - 1;
+    if (pvA && yy >= 0 && yy < H && xx >= 0 && xx < W) {
+        const bf16 *src = x + (ppA + (int64_t)(ky - 1) * W + (kx - 1)) * Ci + c0 + ah;
+        s.a0 = *reinterpret_cast<const uint4 *>(src);
+        s.a1 = *reinterpret_cast<const uint4 *>(src + 8);
+    } else {
+        s.a0 = make_uint4(0u, 0u, 0u, 0u);
+        s.a1 = s.a0;
+    }
+    s.b = make_uint4(0u, 0u, 0u, 0u);
+    if (bact)
+        s.b = *reinterpret_cast<const uint4 *>(w + ((size_t)(co0 + bco) * 9 + tap) * Ci + c0 + bq);
+    return s;
+}
+
+template <int BN>
+__global__ __launch_bounds__(256) void k_conv3x3_lds(const bf16 *__restrict__ x,
+                                                     const bf16 *__restrict__ w,
+                                                     const float *__restrict__ bias,
+                                                     bf16 *__restrict__ y, int N, int H, int W,
+                                                     int Ci, int Co, int relu) {
+    constexpr int BM = 128, NTL = BN / 16;
+    __shared__ __attribute__((aligned(16))) bf16 As[2][BM][kTP];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[2][BN][kTP];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t P = (int64_t)N * H * W;
+    const int64_t base = (int64_t)blockIdx.x * BM;
+    const int co0 = blockIdx.y * BN;
+    // copy roles: input pixel ap (two threads per pixel, 16 channels each);
+    // weight row bco (four threads per row, 8 channels each)
+    const int ap = t >> 1, ah = (t & 1) * 16;
+    const int64_t pA = base + ap;
+    const bool pvA = pA < P;
+    const int64_t ppA = pvA ? pA : 0;
+    const int pxA = (int)(ppA % W), pyA = (int)((ppA / W) % H);
+    const int bco = t >> 2, bq = (t & 3) * 8;
+    const bool bact = bco < BN;
+    const int nck = Ci / 32, K = 9 * nck;
+    f32x4 acc[2][NTL];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < NTL; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    Stage st = conv_gload(x, w, 0, nck, Ci, H, W, pvA, ppA, pyA, pxA, ah, bact, co0, bco, bq);
+    *reinterpret_cast<uint4 *>(&As[0][ap][ah]) = st.a0;
+    *reinterpret_cast<uint4 *>(&As[0][ap][ah + 8]) = st.a1;
+    if (bact) *reinterpret_cast<uint4 *>(&Bs[0][bco][bq]) = st.b;
+    __syncthreads();
+    for (int k = 0; k < K; ++k) {
+        const int buf = k & 1;
+        if (k + 1 < K)
+            st = conv_gload(x, w, k + 1, nck, Ci, H, W, pvA, ppA, pyA, pxA, ah, bact, co0, bco, bq);
+        bf16x8 a[2];
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+            a[m] = *reinterpret_cast<const bf16x8 *>(
+                &As[buf][wave * 32 + m * 16 + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+        for (int n = 0; n < NTL; ++n) {
+            const bf16x8 bv =
+                *reinterpret_cast<const bf16x8 *>(&Bs[buf][n * 16 + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+            for (int m = 0; m < 2; ++m) acc[m][n] = mfma(a[m], bv, acc[m][n]);
+        }
+        if (k + 1 < K) {
+            *reinterpret_cast<uint4 *>(&As[buf ^ 1][ap][ah]) = st.a0;
+            *reinterpret_cast<uint4 *>(&As[buf ^ 1][ap][ah + 8]) = st.a1;
+            if (bact) *reinterpret_cast<uint4 *>(&Bs[buf ^ 1][bco][bq]) = st.b;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int n = 0; n < NTL; ++n) {
+        const int co = co0 + n * 16 + (lane & 15);
+        const float bb = bias ? bias[co] : 0.f;
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t po = base + wave * 32 + m * 16 + 4 * (lane >> 4) + r;
+                if (po < P) {
+                    float v = acc[m][n][r] + bb;
                     if (relu) v = fmaxf(v, 0.f);
                     y[po * Co + co] = (bf16)v;
                 }
@@ -508,25 +621,24 @@ int fwi_nn_conv3x3(const void *x, const void *w, const float *bias, void *y, int
     const bf16 *xb = static_cast<const bf16 *>(x);
     const bf16 *wb = static_cast<const bf16 *>(w);
     bf16 *yb = static_cast<bf16 *>(y);
-    // 64-channel tiles, unless that leaves the chip with fewer than 1024 blocks
-    int nt = Co % 64 == 0 ? 4 : 2;
-    if (nt == 4 && (P + 63) / 64 * (Co / 64) < 1024) nt = 2;
-    const unsigned gy = (unsigned)(Co / (16 * nt));
-    // two 16-pixel tiles per wave when that still gives the chip >= 1024 blocks
-    const bool mt2 = (P + 127) / 128 * gy >= 1024;
-    const unsigned gx = (unsigned)(mt2 ? (P + 127) / 128 : (P + 63) / 64);
-    if (nt == 4 && mt2)
-        hipLaunchKernelGGL((k_conv3x3<4, 2>), dim3(gx, gy), dim3(256), 0, st, xb, wb, bias, yb, N,
-                           H, W, Ci, Co, relu);
-    else if (nt == 4)
-        hipLaunchKernelGGL((k_conv3x3<4, 1>), dim3(gx, gy), dim3(256), 0, st, xb, wb, bias, yb, N,
-                           H, W, Ci, Co, relu);
-    else if (mt2)
-        hipLaunchKernelGGL((k_conv3x3<2, 2>), dim3(gx, gy), dim3(256), 0, st, xb, wb, bias, yb, N,
-                           H, W, Ci, Co, relu);
-    else
-        hipLaunchKernelGGL((k_conv3x3<2, 1>), dim3(gx, gy), dim3(256), 0, st, xb, wb, bias, yb, N,
-                           H, W, Ci, Co, relu);
+    // LDS-tiled kernel when it still gives the chip enough blocks
+    const int bn = Co % 64 == 0 ? 64 : 32;
+    const int64_t lds_blocks = (P + 127) / 128 * (Co / bn);
+    if (lds_blocks >= 256) {
+        const dim3 grid((unsigned)((P + 127) / 128), (unsigned)(Co / bn));
+        if (bn == 64)
+            hipLaunchKernelGGL(k_conv3x3_lds<64>, grid, dim3(256), 0, st, xb, wb, bias, yb, N, H,
+                               W, Ci, Co, relu);
+        else
+            hipLaunchKernelGGL(k_conv3x3_lds<32>, grid, dim3(256), 0, st, xb, wb, bias, yb, N, H,
+                               W, Ci, Co, relu);
+        return status(hipGetLastError());
+    }
+    // small layers: 64-pixel blocks of 32-channel tiles (four times the
+    // blocks of the LDS tiling)
+    const dim3 grid((unsigned)((P + 63) / 64), (unsigned)(Co / 32));
+    hipLaunchKernelGGL((k_conv3x3<2, 1>), grid, dim3(256), 0, st, xb, wb, bias, yb, N, H, W, Ci,
+                       Co, relu);
     return status(hipGetLastError());
 }
 

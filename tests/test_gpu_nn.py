@@ -215,9 +215,11 @@ def test_mse_adam_pack_unpack():
     assert torch.equal(out.cpu().view(N, 2, H, W), ref_out)
 
 
-def test_network_forward_backward_matches_reference():
-    """The whole network on a 2 x 24 x 72 batch (three pooling levels, a
-    ragged 64-pixel tile at level 0) against the rounding-matched reference.
+@pytest.mark.parametrize("N,H,W", [(2, 24, 72), (2, 128, 128)])
+def test_network_forward_backward_matches_reference(N, H, W):
+    """The whole network (2 x 24 x 72: every layer on the small-layer
+    kernel, ragged tiles; 2 x 128 x 128: the full-resolution layers on the
+    LDS-tiled kernel) against the rounding-matched reference.
     A float32 sum that lands on the other side of a bfloat16 rounding
     boundary than the float64 one changes the next layer's sums, which
     flips further roundings, so the two sides drift apart until every
@@ -228,7 +230,6 @@ def test_network_forward_backward_matches_reference():
     each layer's weight and bias gradient; a wrong index or a dropped term
     gives errors of order one."""
     import torch
-    N, H, W = 2, 24, 72
     # a non-zero output layer, so that every layer receives a gradient
     params = nn.init_params(seed=3, out_scale=0.1)
     net = nn.Net(params)
