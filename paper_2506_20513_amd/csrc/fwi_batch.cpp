@@ -77,7 +77,7 @@ void set_bands(Layout &L, int rows) {
         make_tiling(L.d, L);
         return;
     }
-    constexpr int OW = 64 - 2 * kStreamK;
+    constexpr int OW = 64 - 2 * kBatchDepth;
     const int max_bands = (int)(sizeof(L.bands) / sizeof(int)) - 1;
     L.nstrip = (L.d.NX + OW - 1) / OW;
     const int h = std::max(rows, (L.d.NY + max_bands - 1) / max_bands);
@@ -131,9 +131,9 @@ void record(int ip, Problem &p, char *ws, std::vector<Op> &ops) {
             hipError_t r = hipMemcpyAsync(cp, esrc, fbytes, hipMemcpyDeviceToDevice, st);
             return r == hipSuccess ? ok(copy_state(cst, fsrc, d, st)) : r;
         });
-        for (int n = n0; n < n1; n += kStreamK) {
+        for (int n = n0; n < n1; n += kBatchDepth) {
             a.n = n;
-            a.nlev = std::min(kStreamK, n1 - n);
+            a.nlev = std::min(kBatchDepth, n1 - n);
             a.E_in = P.slot(e);
             e ^= 1;
             a.E_out = P.slot(e);
@@ -185,9 +185,9 @@ void record(int ip, Problem &p, char *ws, std::vector<Op> &ops) {
         int fcur = 0, j = 0;
         FwdStreamArgs f = fwd_args(P);
         f.record = 0;
-        for (int n = n0; n < n1; n += kStreamK, ++j) {
+        for (int n = n0; n < n1; n += kBatchDepth, ++j) {
             f.n = n;
-            f.nlev = std::min(kStreamK, n1 - n);
+            f.nlev = std::min(kBatchDepth, n1 - n);
             f.E_in = P.slot(n - n0);
             f.E_lev = P.slot(n + 1 - n0);
             f.E_out = nullptr;
@@ -207,7 +207,7 @@ void record(int ip, Problem &p, char *ws, std::vector<Op> &ops) {
         j = 0;
         for (int n_top = n1; n_top > n0; n_top -= b.nlev, ++j) {
             // passes start at multiples of the depth, as in the single-problem sweep
-            b.nlev = n_top - std::max(n0, (n_top - 1) / kStreamK * kStreamK);
+            b.nlev = n_top - std::max(n0, (n_top - 1) / kBatchDepth * kBatchDepth);
             b.n_top = n_top;
             b.n_base = n0;
             b.E_lev = P.slot(0);
@@ -300,7 +300,7 @@ void build_schedule(std::vector<Problem> &probs, char *ws, size_t area, Schedule
             for (size_t k = i; k < j; ++k) {
                 const Op &q = ops[k];
                 const int nlev = q.kind == OP_FWD ? q.fa.nlev : q.aa.nlev;
-                if ((nlev < kStreamK) != (tail != 0)) continue;
+                if ((nlev < kBatchDepth) != (tail != 0)) continue;
                 const Tiling &tl = q.kind == OP_FWD ? q.fa.tl : q.aa.tl;
                 const int Sq = q.kind == OP_FWD ? q.fa.S : q.aa.S;
                 s.nblocks += stream_blocks(Sq, tl);
@@ -367,10 +367,10 @@ int prepare(int32_t n, const fwi_batch_problem *pp, std::vector<Problem> &probs,
         p.u.geom.rec_ij = p.rec.data();
     }
     // the interval minimising sum_m ceil(nt_m/K) C_m + (K+1) E_m
-    K = (int)std::lround(std::sqrt(num / den) / kStreamK) * kStreamK;
-    K = std::max(K, kStreamK);
+    K = (int)std::lround(std::sqrt(num / den) / kBatchDepth) * kBatchDepth;
+    K = std::max(K, kBatchDepth);
     for (int i = 0; i < n; ++i) {
-        int rc = make_layout(probs[i].d, -1, probs[i].L, K);
+        int rc = make_layout(probs[i].d, -1, probs[i].L, K, kBatchDepth);
         if (rc != FWI_OK) return rc;
     }
     return FWI_OK;

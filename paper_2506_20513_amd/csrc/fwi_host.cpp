@@ -80,15 +80,20 @@ int make_dims(const fwi_grid *grid, const fwi_geom *geom, Dims &d) {
     return check_geom(geom, d);
 }
 
+// Temporal depth of a single problem's streaming passes (see kDepthLarge).
+int stream_depth(const Dims &d) {
+    return (long long)d.NX * d.NY >= kDepthLargeCells ? kDepthLarge : kDepthSmall;
+}
+
 // Checkpoint interval minimising checkpoints + segment buffer,
 // ceil(nt/K) * C + (K+1) * E with C one full state and E one Ez slot, rounded
-// to a multiple of the streaming depth so segments split into full passes.
-int choose_k(const Dims &d) {
+// to a multiple of the temporal depth so segments split into full passes.
+int choose_k(const Dims &d, int depth) {
     const double C = 3.0 * d.plane + 2.0 * d.xs + 2.0 * d.ys;
     const double E = (double)d.plane;
     const double k = std::sqrt((double)d.nt * C / E);
-    int K = (int)std::lround(k / kStreamK) * kStreamK;
-    K = std::max(K, kStreamK);
+    int K = (int)std::lround(k / depth) * depth;
+    K = std::max(K, depth);
     return std::max(1, std::min(K, d.nt));
 }
 
@@ -97,7 +102,7 @@ int choose_k(const Dims &d) {
 // rows of start-up on top of its own rows, and a last partial round of waves
 // leaves SIMDs idle; pick the band count with the least estimated time.
 void make_tiling(const Dims &d, Layout &L) {
-    constexpr int K = kStreamK, OW = 64 - 2 * K;
+    const int K = L.depth, OW = 64 - 2 * K;
     const int max_bands = (int)(sizeof(L.bands) / sizeof(int)) - 1;
     const double slots = 1024.0 * 4.0;   // 256 CUs x 4 SIMDs x ~4 resident waves
     L.nstrip = (d.NX + OW - 1) / OW;
@@ -121,12 +126,13 @@ void make_tiling(const Dims &d, Layout &L) {
 }
 
 // Workspace layout for a mode (FWI_SAVE_* or -1 = fwi_gradient).
-int make_layout(const Dims &d, int mode, Layout &L, int k) {
+int make_layout(const Dims &d, int mode, Layout &L, int k, int depth) {
     if (mode != FWI_SAVE_NONE && mode != FWI_SAVE_CHECKPOINT &&
         mode != FWI_SAVE_HISTORY && mode != -1)
         return FWI_EINVAL;
     L.d = d;
     L.mode = mode;
+    L.depth = depth > 0 ? depth : stream_depth(d);
     const size_t S = (size_t)d.S;
     const size_t field = S * d.plane * sizeof(float);
     const size_t xs = S * d.xs * sizeof(float), ys = S * d.ys * sizeof(float);
@@ -158,7 +164,7 @@ int make_layout(const Dims &d, int mode, Layout &L, int k) {
     } else if (mode == FWI_SAVE_HISTORY) {
         L.nslots = d.nt + 1;
     } else {
-        L.K = k > 0 ? std::min(k, d.nt) : choose_k(d);
+        L.K = k > 0 ? std::min(k, d.nt) : choose_k(d, L.depth);
         L.ncp = (d.nt + L.K - 1) / L.K;
         L.nslots = L.K + 1;
     }
@@ -264,6 +270,7 @@ Tiling tiling(const Ptrs &P) {
     t.bands = P.i(L.off_bands);
     t.nstrip = L.nstrip;
     t.nband = L.nband;
+    t.depth = L.depth;
     return t;
 }
 
@@ -422,7 +429,7 @@ int setup(const Ptrs &P, const fwi_geom *g, const StreamCold &cold, const float 
     return FWI_OK;
 }
 
-// Forward steps [n0, n1) in passes of up to kStreamK steps.  E of the pass
+// Forward steps [n0, n1) in passes of up to L.depth steps.  E of the pass
 // starting at n is read from ein(n); per-level E goes to elev(n) (history /
 // segment) or, when elev returns null, the final E of the pass to eout(n).
 // The H / CPML state ping-pongs between fwd[cur] and fwd[cur ^ 1].
@@ -433,9 +440,9 @@ int forward_passes(const Ptrs &P, FwdStreamArgs a, int n0, int n1, int &cur, EIn
     State fs[2] = {P.state(L.off_fwd[0], false), P.state(L.off_fwd[1], false)};
     a.record = record ? 1 : 0;
     const double all = (double)L.d.NX * L.d.NY * L.d.S;
-    for (int n = n0; n < n1; n += kStreamK) {
+    for (int n = n0; n < n1; n += L.depth) {
         a.n = n;
-        a.nlev = std::min(kStreamK, n1 - n);
+        a.nlev = std::min(L.depth, n1 - n);
         a.E_in = ein(n);
         a.E_lev = elev(n);
         a.E_out = a.E_lev ? nullptr : eout(n);
@@ -518,7 +525,7 @@ int do_adjoint(const Layout &L, const float *eps_r, const float *sigma, float *g
     // every rounding, is the same for any checkpoint interval.
     auto adj_range = [&](int n_hi, int n_lo) -> int {
         for (int n_top = n_hi; n_top > n_lo; n_top -= a.nlev) {
-            a.nlev = n_top - std::max(n_lo, (n_top - 1) / kStreamK * kStreamK);
+            a.nlev = n_top - std::max(n_lo, (n_top - 1) / L.depth * L.depth);
             a.n_top = n_top;
             a.n_base = n_lo;
             a.E_lev = P.slot(0);
@@ -601,7 +608,7 @@ extern "C" int fwi_checkpoint_interval(const fwi_grid *grid, const fwi_geom *geo
     Dims d;
     int rc = make_dims(grid, geom, d);
     if (rc != FWI_OK) return rc;
-    *k = choose_k(d);
+    *k = choose_k(d, stream_depth(d));
     return FWI_OK;
 }
 

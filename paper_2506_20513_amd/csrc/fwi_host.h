@@ -16,12 +16,13 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // Validate the grid and geometry and derive the dimensions (FWI_* status).
 int make_dims(const fwi_grid *grid, const fwi_geom *geom, Dims &d);
 // Checkpoint interval minimising checkpoint plus segment-buffer memory.
-int choose_k(const Dims &d);
+int stream_depth(const Dims &d);
+int choose_k(const Dims &d, int depth);
 // Row bands of the streaming decomposition (stored in L).
 void make_tiling(const Dims &d, Layout &L);
 // Workspace layout for a save mode (-1: fwi_gradient); k > 0 forces the
 // checkpoint interval (a multiple of the streaming depth).
-int make_layout(const Dims &d, int mode, Layout &L, int k = 0);
+int make_layout(const Dims &d, int mode, Layout &L, int k = 0, int depth = 0);
 
 // Pointers into the workspace.
 struct Ptrs {

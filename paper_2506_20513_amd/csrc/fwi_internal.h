@@ -58,6 +58,7 @@ struct Layout {
     Dims d;
     int mode;          // FWI_SAVE_* or -1 for fwi_gradient
     int K;             // checkpoint interval (checkpoint modes)
+    int depth;         // temporal depth of the streaming passes
     int ncp;           // number of checkpoints
     int nslots;        // Ez slots
     // streaming decomposition (see Tiling)
@@ -77,8 +78,19 @@ struct Layout {
 
 // ---- kernel argument blocks -------------------------------------------------
 
-// Time levels advanced per pass of the streaming kernels.
-constexpr int kStreamK = 4;
+// Time levels advanced per pass of the streaming kernels (temporal depth).
+// Depth 8 reads and writes each field row once per 8 steps, but the
+// dependency cone leaves a 64-lane strip 48 output columns (16 recomputed)
+// and the kernels need 103-159 VGPRs; depth 4 keeps 56 columns and 72-93
+// VGPRs.  Measured: depth 8 gives 5-7% more cell-updates per second on a
+// 2088x1064 grid, and is 12-38% slower on grids of 0.02-0.25 M cells, where
+// the longer pipeline start of every band weighs more.  A problem uses depth
+// 8 from kDepthLargeCells cells per shot on.  Batched problems always use
+// depth 4 (one depth for all merged passes).
+constexpr int kDepthSmall = 4;
+constexpr int kDepthLarge = 8;
+constexpr long long kDepthLargeCells = 1LL << 20;
+constexpr int kBatchDepth = kDepthSmall;
 
 // Source and receiver tables on the device.  Receivers of each shot are
 // sorted by (row, column), stable in receiver index; rrow is the row CSR.
@@ -96,6 +108,7 @@ struct StreamGeom {
 struct Tiling {
     const int *bands;         // [nband + 1]
     int nstrip, nband;
+    int depth;                // temporal depth: kDepthSmall or kDepthLarge
 };
 
 // Per-call constants of the stencil kernels that only rare branches read
@@ -167,7 +180,7 @@ hipError_t launch_adj_stream(const AdjStreamArgs &a, hipStream_t st);
 unsigned stream_blocks(int S, const Tiling &tl);
 // One pass for nm problems at once: tab[m] (device) holds problem m's
 // arguments and boff[0..nm] (device) the prefix sums of their block counts,
-// nblocks = boff[nm].  tail: some problem advances fewer than kStreamK levels.
+// nblocks = boff[nm].  tail: some problem advances fewer than kBatchDepth levels.
 hipError_t launch_fwd_table(const FwdStreamArgs *tab, const unsigned *boff, int nm,
                             unsigned nblocks, bool tail, hipStream_t st);
 hipError_t launch_adj_table(const AdjStreamArgs *tab, const unsigned *boff, int nm,

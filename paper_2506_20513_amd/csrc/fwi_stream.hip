@@ -629,9 +629,9 @@ hipError_t launch_fwd_table(const FwdStreamArgs *tab, const unsigned *boff, int 
                             unsigned nblocks, bool tail, hipStream_t st) {
     if (nblocks == 0) return hipSuccess;
     if (tail)
-        hipLaunchKernelGGL((k_fwd_tab<kStreamK, true>), dim3(nblocks), dim3(64), 0, st, tab, boff, nm);
+        hipLaunchKernelGGL((k_fwd_tab<kBatchDepth, true>), dim3(nblocks), dim3(64), 0, st, tab, boff, nm);
     else
-        hipLaunchKernelGGL((k_fwd_tab<kStreamK, false>), dim3(nblocks), dim3(64), 0, st, tab, boff, nm);
+        hipLaunchKernelGGL((k_fwd_tab<kBatchDepth, false>), dim3(nblocks), dim3(64), 0, st, tab, boff, nm);
     return hipGetLastError();
 }
 
@@ -639,28 +639,46 @@ hipError_t launch_adj_table(const AdjStreamArgs *tab, const unsigned *boff, int 
                             unsigned nblocks, bool tail, hipStream_t st) {
     if (nblocks == 0) return hipSuccess;
     if (tail)
-        hipLaunchKernelGGL((k_adj_tab<kStreamK, true>), dim3(nblocks), dim3(64), 0, st, tab, boff, nm);
+        hipLaunchKernelGGL((k_adj_tab<kBatchDepth, true>), dim3(nblocks), dim3(64), 0, st, tab, boff, nm);
     else
-        hipLaunchKernelGGL((k_adj_tab<kStreamK, false>), dim3(nblocks), dim3(64), 0, st, tab, boff, nm);
+        hipLaunchKernelGGL((k_adj_tab<kBatchDepth, false>), dim3(nblocks), dim3(64), 0, st, tab, boff, nm);
+    return hipGetLastError();
+}
+
+// Single-problem passes at the problem's temporal depth (a.tl.depth);
+// nlev < depth takes the partial-pass variant.
+template <int K>
+hipError_t launch_fwd_depth(const FwdStreamArgs &a, unsigned nb, hipStream_t st) {
+    if (a.nlev == K)
+        hipLaunchKernelGGL((k_fwd<K, false>), dim3(nb), dim3(64), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_fwd<K, true>), dim3(nb), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int K>
+hipError_t launch_adj_depth(const AdjStreamArgs &a, unsigned nb, hipStream_t st) {
+    if (a.nlev == K)
+        hipLaunchKernelGGL((k_adj<K, false>), dim3(nb), dim3(64), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_adj<K, true>), dim3(nb), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_fwd_stream(const FwdStreamArgs &a, hipStream_t st) {
     const unsigned nb = (unsigned)a.S * a.tl.nstrip * a.tl.nband;
-    if (a.nlev == kStreamK)
-        hipLaunchKernelGGL((k_fwd<kStreamK, false>), dim3(nb), dim3(64), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_fwd<kStreamK, true>), dim3(nb), dim3(64), 0, st, a);
-    return hipGetLastError();
+    if (a.nlev < 1 || a.nlev > a.tl.depth) return hipErrorInvalidValue;
+    if (a.tl.depth == kDepthLarge) return launch_fwd_depth<kDepthLarge>(a, nb, st);
+    if (a.tl.depth == kDepthSmall) return launch_fwd_depth<kDepthSmall>(a, nb, st);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_adj_stream(const AdjStreamArgs &a, hipStream_t st) {
     const unsigned nb = (unsigned)a.S * a.tl.nstrip * a.tl.nband;
-    if (a.nlev == kStreamK)
-        hipLaunchKernelGGL((k_adj<kStreamK, false>), dim3(nb), dim3(64), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_adj<kStreamK, true>), dim3(nb), dim3(64), 0, st, a);
-    return hipGetLastError();
+    if (a.nlev < 1 || a.nlev > a.tl.depth) return hipErrorInvalidValue;
+    if (a.tl.depth == kDepthLarge) return launch_adj_depth<kDepthLarge>(a, nb, st);
+    if (a.tl.depth == kDepthSmall) return launch_adj_depth<kDepthSmall>(a, nb, st);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace fwi

@@ -311,3 +311,14 @@ def test_tv_argument_checks():
     assert L.fwi_tv_gradient(A, A, 2, 16, 24, one, one, one, 3, None, need, None) == -4
     assert L.fwi_tv_gradient(A, A, 2, 16, 24, one, one, one, 3, A + 64, need, None) == -4
     assert L.fwi_tv_gradient(A, A, 2, 16, 24, one, one, one, 3, A, need - 1, None) == -4
+
+
+def test_checkpoint_interval_follows_the_temporal_depth():
+    """Grids from 2^20 cells per shot on stream at depth 8, smaller ones at
+    depth 4; the checkpoint interval is a multiple of the depth."""
+    for cfg, depth in ((I.config_tiny(), 4), (I.config_survey(), 4), (I.config_large(), 8),
+                       (I.config_tiny().with_(nx=1004, ny=1004, nt=203), 8)):
+        src, rec = I.geometry(cfg)
+        g = fwi.Geometry(src, rec, FAKE)
+        k = fwi.checkpoint_interval(fwi.grid_from_config(cfg), g)
+        assert k % depth == 0 and k <= cfg.nt, (cfg.name, k)

@@ -112,6 +112,32 @@ def test_checkpoint_and_history_agree_bitwise_ragged_nt(nt):
         assert np.array_equal(a, b)
 
 
+def test_checkpoint_and_history_agree_bitwise_depth8():
+    """The same on a grid of 2^20 cells (1024 x 1024 total), which runs its
+    streaming passes at temporal depth 8; nt = 203 is ragged against both
+    the depth and the checkpoint interval."""
+    c = make_case(I.config_tiny().with_(nx=1004, ny=1004, nt=203))
+    r = run_of(c)
+    k = fwi.checkpoint_interval(r.grid, r.geom)
+    print("checkpoint interval", k, flush=True)
+    assert k % 8 == 0
+    out = {}
+    for mode in (fwi.FWI_SAVE_HISTORY, fwi.FWI_SAVE_CHECKPOINT):
+        tr, ws = r.forward(mode)
+        res = tr - r.torch.from_numpy(c["obs"]).to(r.dev)
+        ge, gs, sa = r.adjoint(res, mode, ws, want_src_adjoint=True)
+        out[mode] = (np_(tr), np_(ge), np_(gs), np_(sa))
+        del ws
+    for a, b in zip(out[fwi.FWI_SAVE_HISTORY], out[fwi.FWI_SAVE_CHECKPOINT]):
+        assert np.array_equal(a, b)
+    # and the traces against the oracle at this size
+    rt = run_of(c, "true")
+    tr, _ = rt.forward()
+    err = rel_l2(np_(tr), c["obs"])
+    print("depth-8 traces rel L2", err, flush=True)
+    assert err <= TR_TOL
+
+
 def test_gradient_entry_point_matches_forward_adjoint(tiny):
     r = run_of(tiny)
     mis, ge, gs, tr = r.gradient(tiny["obs"])
