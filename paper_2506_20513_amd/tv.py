@@ -66,3 +66,46 @@ class TV:
         if st != 0:
             raise fwi.FwiError(st, "fwi_tv_gradient")
         return grad
+
+
+BYTES_PER_CELL_ITER = 28   # read U, Bx, By, X; write U, Bx, By (float32)
+
+
+def main(argv=None):
+    """Throughput of the Algorithm 3 kernel: eps_r and sigma fields of the
+    given size, `iters` iterations per call."""
+    import argparse
+    import json
+    import sys
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--size", default="1064x2088", help="field rows x columns")
+    ap.add_argument("--iters", type=int, default=50)
+    ap.add_argument("--reps", type=int, default=5)
+    args = ap.parse_args(argv)
+    if not torch.cuda.is_available():
+        print("tv: no GPU visible", file=sys.stderr)
+        return 1
+    ny, nx = (int(v) for v in args.size.split("x"))
+    g = torch.Generator(device="cuda").manual_seed(0)
+    X = torch.rand(2, ny, nx, generator=g, device="cuda") * torch.tensor([17.0, 0.05], device="cuda")[:, None, None] + torch.tensor([3.0, 0.001], device="cuda")[:, None, None]
+    G = torch.zeros_like(X)
+    op = TV(2, ny, nx, 8.0, 2.0, 1e-3, args.iters)
+    op(X, G)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.reps):
+        op(X, G)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.reps
+    per_iter = ms / args.iters
+    gbps = BYTES_PER_CELL_ITER * 2 * ny * nx / (per_iter * 1e-3) / 1e9
+    print(json.dumps({"fields": 2, "shape": [ny, nx], "iters": args.iters, "ms_per_call": round(ms, 4),
+                      "ms_per_iteration": round(per_iter, 5), "algorithmic_GBps": round(gbps, 1),
+                      "frac_of_8TBps": round(gbps / 8000.0, 3)}), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
