@@ -311,12 +311,37 @@ def feature_planes(obj: Objective, x, g, gscale):
     return planes.contiguous(), sc
 
 
+# The grid spacing and centre frequency of the training models: the network
+# has learnt features of a given size in wavelengths per cell.
+TRAIN_DX = 0.02
+TRAIN_F0 = 200e6
+
+
+def wavelength_factor(dx: float, f0: float) -> int:
+    """Power-of-two resampling factor that brings a model sampled at dx with
+    a source of centre frequency f0 to the training models' cells per
+    wavelength (the wavelength in cells scales as 1 / (f0 dx))."""
+    r = (TRAIN_F0 * TRAIN_DX) / (f0 * dx)
+    f = 1
+    while f * 2 <= r * 1.4142135623730951:
+        f *= 2
+    return f
+
+
 class Preconditioner:
     """The trained network applied to one iterate: x, g -> proposed step
-    (flat like x, zero on the fixed rows)."""
+    (flat like x, zero on the fixed rows).
 
-    def __init__(self, net: nn.Net):
+    factor > 1 applies the network at the training models' cells per
+    wavelength: the packed input is average-pooled `factor` times smaller
+    (pooling kernel), the network runs on it, and its output is brought
+    back by nearest upsampling (upsampling kernel)."""
+
+    def __init__(self, net: nn.Net, factor: int = 1):
+        if factor < 1 or factor & (factor - 1):
+            raise ValueError("factor must be a power of two")
         self.net = net
+        self.factor = factor
         self.calls = 0
         self.seconds = 0.0
         self.gscale = None
@@ -329,9 +354,20 @@ class Preconditioner:
             self.gscale = gradient_scales(obj, g)
         planes, sc = feature_planes(obj, x, g, self.gscale)
         H, W = obj.ny, obj.nx
+        if H % (8 * self.factor) or W % (8 * self.factor):
+            raise ValueError(f"interior {H}x{W} is not a multiple of {8 * self.factor}")
         xin = torch.empty(H * W * nn.CPAD, dtype=torch.bfloat16, device=x.device)
         nn.pack4(planes, sc, xin, 1, H, W)
-        y = self.net.forward(xin, 1, H, W)
+        h, w = H, W
+        while h > H // self.factor:
+            xd = torch.empty((h // 2) * (w // 2) * nn.CPAD, dtype=torch.bfloat16, device=x.device)
+            nn.pool2(xin, xd, 1, h, w, nn.CPAD)
+            xin, h, w = xd, h // 2, w // 2
+        y = self.net.forward(xin, 1, h, w)
+        while h < H:
+            yu = torch.empty((2 * h) * (2 * w) * nn.CPAD, dtype=torch.bfloat16, device=x.device)
+            nn.up2_add(y, None, yu, 1, 2 * h, 2 * w, nn.CPAD)
+            y, h, w = yu, 2 * h, 2 * w
         out = torch.empty(2 * H * W, dtype=torch.float32, device=x.device)
         nn.unpack2(y, torch.ones(2, device=x.device), out, 1, H, W, nn.CPAD)
         d = torch.where(obj.free, out.to(x.dtype), torch.zeros_like(x))
@@ -475,14 +511,16 @@ def compare(net: nn.Net, problems, iters: int, st: FL.Settings, log=print,
     Returns one record per problem with both wall-clock times.  verbose:
     log every iterate."""
     out = []
-    for name, prob, obs, e0, s0 in problems:
+    for item in problems:
+        name, prob, obs, e0, s0 = item[:5]
+        factor = item[5] if len(item) > 5 else 1
         obj = Objective(prob, obs, e0, s0, st)
         if verbose and log:
             log(f"{name}: plain L-BFGS")
         plain = minimise(obj, iters, log=log if verbose else None)
         target = plain.final_f
         objn = Objective(prob, obs, e0, s0, st)
-        pc = Preconditioner(net)
+        pc = Preconditioner(net, factor)
         if verbose and log:
             log(f"{name}: learned, until f <= {target:.6g}")
         learned = minimise(objn, 2 * iters, proposer=lambda x, g: pc(objn, x, g),
@@ -496,6 +534,7 @@ def compare(net: nn.Net, problems, iters: int, st: FL.Settings, log=print,
                "learned_reached_plain_final": bool(reached),
                "learned_iterations": learned.log[-1].k,
                "net_steps_accepted": sum(1 for it in learned.log if it.source == "net"),
+               "resampling_factor": factor,
                "net_seconds": round(pc.seconds, 3)}
         if log:
             log(f"compare: {rec}")
@@ -503,7 +542,7 @@ def compare(net: nn.Net, problems, iters: int, st: FL.Settings, log=print,
     return out
 
 
-def _survey_problem(cfg):
+def _survey_problem(cfg, factor=None):
     from . import fwi
     from . import inputs as I
     e, s, e0, s0 = I.model_for(cfg)
@@ -512,7 +551,8 @@ def _survey_problem(cfg):
     prob = AG.Problem(fwi.grid_from_config(cfg), src, rec, w)
     with torch.no_grad():
         obs = AG.traces(prob, torch.from_numpy(e).cuda(), torch.from_numpy(s).cuda())
-    return (cfg.name, prob, obs, torch.from_numpy(e0).cuda(), torch.from_numpy(s0).cuda())
+    f = wavelength_factor(cfg.dx, cfg.f0) if not factor else factor
+    return (cfg.name, prob, obs, torch.from_numpy(e0).cuda(), torch.from_numpy(s0).cuda(), f)
 
 
 def _summary(res):
@@ -536,6 +576,10 @@ def main(argv=None):
     ap.add_argument("--large", action="store_true", help="also compare on the 2048x1024 model")
     ap.add_argument("--large-iters", type=int, default=5)
     ap.add_argument("--save", default=None, help="write the trained parameters (.npy)")
+    ap.add_argument("--factor", type=int, default=1,
+                    help="resampling factor of the network on the survey and large models; 0 = "
+                         "matched to the training models' cells per wavelength (2 on the large "
+                         "model, where it measured slower than 1)")
     ap.add_argument("--load", default=None,
                     help="trained parameters (.npy) to use instead of generating and training")
     args = ap.parse_args(argv)
@@ -569,13 +613,15 @@ def main(argv=None):
     del problems
     from . import inputs as I
     if args.survey:
-        r = compare(net, [_survey_problem(I.config_survey())], args.survey_iters, st, log=err,
+        r = compare(net, [_survey_problem(I.config_survey(), args.factor)], args.survey_iters, st,
+                    log=err,
                     verbose=True)
         out["compare_survey"] = r
     if args.large:
         torch.cuda.empty_cache()
         err("large: building the problem (observed traces)")
-        r = compare(net, [_survey_problem(I.config_large())], args.large_iters, st, log=err,
+        r = compare(net, [_survey_problem(I.config_large(), args.factor)], args.large_iters, st,
+                    log=err,
                     verbose=True)
         out["compare_large"] = r
     print(json.dumps(out), flush=True)

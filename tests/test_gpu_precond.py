@@ -51,3 +51,12 @@ def test_pairs_training_and_learned_inversion():
     fs = [it.f for it in run.log]
     assert all(b <= a for a, b in zip(fs, fs[1:]))
     assert pc.calls >= 1
+    # applied at half resolution (pool, network, upsample): a finite proposal
+    # of the model's shape, zero on the fixed surface rows, constant on 2x2 blocks
+    pc2 = PC.Preconditioner(net, 2)
+    f0, g0 = obj(obj.x0)
+    d = pc2(obj, obj.x0, g0)
+    assert d.shape == obj.x0.shape and torch.isfinite(d).all()
+    assert float(d[~obj.free].abs().max()) == 0.0
+    u = d[: obj.ny * obj.nx].view(obj.ny, obj.nx)[8:, :]
+    assert torch.equal(u[0::2, 0::2], u[1::2, 1::2])

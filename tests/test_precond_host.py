@@ -116,3 +116,13 @@ def test_target_stops_the_run():
     tgt = full.log[10].f
     part = PC.minimise(Quadratic(seed=5), 50, target_f=tgt)
     assert part.final_f <= tgt and part.log[-1].k == 10
+
+
+def test_wavelength_factor():
+    """Models with more cells per wavelength than the training ones are
+    resampled by the nearest power of two (cells per wavelength ~ 1/(f0 dx))."""
+    assert PC.wavelength_factor(0.02, 200e6) == 1          # the training models
+    assert PC.wavelength_factor(0.01, 400e6) == 1          # same cells per wavelength
+    assert PC.wavelength_factor(0.005, 400e6) == 2         # twice as many
+    assert PC.wavelength_factor(0.005, 200e6) == 4
+    assert PC.wavelength_factor(0.04, 200e6) == 1          # coarser: never upsampled
