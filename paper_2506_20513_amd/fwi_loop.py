@@ -20,6 +20,7 @@ import sys
 import time
 from dataclasses import dataclass, field
 
+import numpy as np
 import torch
 import torch.nn.functional as F
 
@@ -118,10 +119,12 @@ class Result:
 
 def invert(prob: AG.Problem, wavelet_full: torch.Tensor, observed_full: torch.Tensor,
            eps0: torch.Tensor, sig0: torch.Tensor, settings: Settings, dt: float,
-           log=print) -> Result:
+           log=print, progress=None, on_band_end=None) -> Result:
     """Invert for (eps_r, sigma) over the interior.  eps0 / sig0: initial
     total-grid models [NY][NX]; wavelet_full [S][nt] and observed_full
-    [S][nt][R] at full band."""
+    [S][nt][R] at full band.  progress(record) is called after every
+    misfit evaluation; on_band_end(band_Hz, eps_r, sigma, result) after
+    every band with the current total-grid models (for snapshots)."""
     st = settings
     npml = prob.grid.npml
     NY, NX = prob.model_shape
@@ -186,6 +189,8 @@ def invert(prob: AG.Problem, wavelet_full: torch.Tensor, observed_full: torch.Te
             res.evaluations += 1
             res.history.append(Record(float(fc or 0), it[0], float(J.detach()),
                                       float(J.detach()) / J0[0], time.perf_counter() - t_start))
+            if progress is not None:
+                progress(res.history[-1])
             it[0] += 1
             return loss
 
@@ -216,6 +221,9 @@ def invert(prob: AG.Problem, wavelet_full: torch.Tensor, observed_full: torch.Te
         last = res.history[-1]
         log(f"band {fc / 1e6 if fc else 0:.0f} MHz: {res.evaluations} evaluations so far, "
             f"relative misfit {last.rel_misfit:.4f}, {last.seconds:.1f} s")
+        if on_band_end is not None:
+            e, s, _, _ = models()
+            on_band_end(float(fc or 0), e.detach(), s.detach(), res)
     e, s, _, _ = models()
     res.eps_r, res.sigma = e.detach(), s.detach()
     res.seconds = time.perf_counter() - t_start
@@ -238,6 +246,11 @@ def main(argv=None):
     ap.add_argument("--tv-mode", default="smooth", choices=["smooth", "admm"])
     ap.add_argument("--recipe", default=None, choices=["paper"],
                     help="the paper's Adam schedule with Algorithm 3 TV (overrides the rest)")
+    ap.add_argument("--init-model", default=None,
+                    help="start from a snapshot (.npz with eps_r, sigma on the total grid)")
+    ap.add_argument("--snapshot", default=None,
+                    help="write the models after every band to this .npz (resume with --init-model)")
+    ap.add_argument("--verbose", action="store_true", help="log every misfit evaluation")
     args = ap.parse_args(argv)
     if not torch.cuda.is_available():
         print("fwi_loop: no GPU visible", file=sys.stderr)
@@ -262,8 +275,32 @@ def main(argv=None):
         st = Settings(bands=bands, iters=args.iters, optimizer=args.optimizer, tv_weight=args.tv,
                       tv_mode=args.tv_mode)
     et, stt = torch.from_numpy(e).cuda(), torch.from_numpy(s).cuda()
-    r = invert(prob, w, obs, torch.from_numpy(e0).cuda(), torch.from_numpy(s0).cuda(), st, cfg.dt,
-               log=lambda m: print(m, file=sys.stderr, flush=True))
+    err = lambda m: print(m, file=sys.stderr, flush=True)
+    start_e, start_s = torch.from_numpy(e0).cuda(), torch.from_numpy(s0).cuda()
+    if args.init_model:
+        with np.load(args.init_model, allow_pickle=False) as z:
+            start_e = torch.from_numpy(np.ascontiguousarray(z["eps_r"], np.float32)).cuda()
+            start_s = torch.from_numpy(np.ascontiguousarray(z["sigma"], np.float32)).cuda()
+        if tuple(start_e.shape) != (cfg.NY, cfg.NX) or tuple(start_s.shape) != (cfg.NY, cfg.NX):
+            raise SystemExit(f"{args.init_model}: models are not {cfg.NY}x{cfg.NX}")
+    bands_done = []
+
+    def band_end(fc, e_now, s_now, res):
+        h = [x for x in res.history if x.band == fc]
+        bands_done.append({"band_Hz": fc, "evaluations": len(h),
+                           "relative_misfit_end": h[-1].rel_misfit if h else None,
+                           "seconds_at_end": round(h[-1].seconds, 2) if h else None})
+        if args.snapshot:
+            np.savez(args.snapshot, eps_r=e_now.cpu().numpy(), sigma=s_now.cpu().numpy(),
+                     band_Hz=np.float64(fc), evaluations=np.int64(res.evaluations))
+            err(f"snapshot after band {fc / 1e6:.0f} MHz -> {args.snapshot}")
+
+    prog = None
+    if args.verbose:
+        prog = lambda r: err(f"  band {r.band / 1e6:.0f} MHz evaluation {r.it}: relative misfit "
+                             f"{r.rel_misfit:.5f}, {r.seconds:.1f} s")
+    r = invert(prob, w, obs, start_e, start_s, st, cfg.dt, log=err, progress=prog,
+               on_band_end=band_end)
     sl = (slice(cfg.npml, cfg.NY - cfg.npml), slice(cfg.npml, cfg.NX - cfg.npml))
 
     def rel(a, b):
@@ -275,9 +312,10 @@ def main(argv=None):
            "seconds": round(r.seconds, 2),
            "seconds_per_evaluation": round(r.seconds / max(1, r.evaluations), 4),
            "final_relative_misfit_last_band": r.history[-1].rel_misfit,
-           "eps_model_error_initial": rel(torch.from_numpy(e0).cuda(), et),
+           "init_model": args.init_model, "bands": bands_done,
+           "eps_model_error_start": rel(start_e, et),
            "eps_model_error_final": rel(r.eps_r, et),
-           "sigma_model_error_initial": rel(torch.from_numpy(s0).cuda(), stt),
+           "sigma_model_error_start": rel(start_s, stt),
            "sigma_model_error_final": rel(r.sigma, stt)}
     print(json.dumps(out), flush=True)
     return 0

@@ -148,3 +148,21 @@ def test_paper_recipe_adam_with_algorithm3_tv(case):
     with pytest.raises(ValueError):
         L.invert(prob, case["w"], case["obs"], case["e0"], case["s0"],
                  L.Settings(bands=(None,), iters=1, tv_mode="admm"), cfg.dt, log=seen.append)
+
+
+def test_driver_snapshot_and_resume(tmp_path, capsys):
+    """The driver writes the models after every band and a second run
+    resumes from that snapshot (its starting model error is the first run's
+    final one)."""
+    import json
+    from paper_2506_20513_amd import fwi_loop as L
+    snap = str(tmp_path / "snap.npz")
+    assert L.main(["--workload", "tiny", "--bands", "100e6", "--iters", "3",
+                   "--snapshot", snap]) == 0
+    first = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    assert first["bands"][0]["evaluations"] >= 1
+    assert L.main(["--workload", "tiny", "--bands", "full", "--iters", "2",
+                   "--init-model", snap]) == 0
+    second = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    assert abs(second["eps_model_error_start"] - first["eps_model_error_final"]) <= 1e-6
+    assert second["init_model"] == snap
