@@ -54,11 +54,35 @@ def total_variation(x: torch.Tensor, delta: float = 1e-3) -> torch.Tensor:
     return torch.sqrt(dx * dx + dy * dy + delta * delta).mean()
 
 
+class _PadReplicate(torch.autograd.Function):
+    """Edge replication with an explicit adjoint: the gradient of every
+    replicated cell is summed into the edge cell it copies, by fixed-order
+    reductions over the CPML strips (torch's own replicate-pad backward
+    accumulates with atomics, so its sums land in varying order)."""
+
+    @staticmethod
+    def forward(ctx, x, npml):
+        ctx.npml = npml
+        return F.pad(x[None, None], (npml, npml, npml, npml), mode="replicate")[0, 0]
+
+    @staticmethod
+    def backward(ctx, gy):
+        p = ctx.npml
+        g1 = gy[:, p:-p].clone()                       # [NY][nx]
+        g1[:, 0] += gy[:, :p].sum(dim=1)
+        g1[:, -1] += gy[:, -p:].sum(dim=1)
+        gx = g1[p:-p, :].clone()                       # [ny][nx]
+        gx[0, :] += g1[:p, :].sum(dim=0)
+        gx[-1, :] += g1[-p:, :].sum(dim=0)
+        return gx, None
+
+
 def pad_interior(x: torch.Tensor, npml: int) -> torch.Tensor:
-    """Interior [ny][nx] -> total grid [ny+2npml][nx+2npml] by edge replication."""
+    """Interior [ny][nx] -> total grid [ny+2npml][nx+2npml] by edge
+    replication (deterministic gradient)."""
     if npml == 0:
         return x
-    return F.pad(x[None, None], (npml, npml, npml, npml), mode="replicate")[0, 0]
+    return _PadReplicate.apply(x, npml)
 
 
 # ---------------------------------------------------------------------------

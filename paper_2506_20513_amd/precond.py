@@ -406,38 +406,91 @@ def tiny_problem(seed: int, smoothing: float, device="cuda"):
     return cfg, prob, obs, T(e), T(s), T(e0), T(s0)
 
 
+def _one_run(r: int, seed0: int, iters: int, st: FL.Settings, smoothing: float, device):
+    """Pairs of plain run r: features at every iterate but the last, and the
+    update from there to the last iterate."""
+    cfg, prob, obs, e, s, e0, s0 = tiny_problem(seed0 + r, smoothing, device)
+    obj = Objective(prob, obs, e0, s0, st)
+    run = minimise(obj, iters, keep=True)
+    xK = run.xs[-1]
+    n = obj.ny * obj.nx
+    gsc = gradient_scales(obj, run.gs[0])
+    planes, scales, targets = [], [], []
+    for xk, gk in zip(run.xs[:-1], run.gs[:-1]):
+        p, sc = feature_planes(obj, xk, gk, gsc)
+        planes.append(p)
+        scales.append(sc)
+        dx = (xK - xk).float()
+        targets.append(torch.stack([dx[:n], dx[n:]], dim=-1).view(obj.ny, obj.nx, 2))
+    return planes, scales, targets, obj.evals, run.log[-1].J / obj.J0
+
+
 def generate(nruns: int, iters: int, seed0: int, st: FL.Settings, log=print,
-             device="cuda") -> tuple[Dataset, dict]:
+             device="cuda", workers: int = 1) -> tuple[Dataset, dict]:
     """Pairs from nruns plain L-BFGS runs on seeded 128x128 models (seeds
     seed0 .. seed0 + nruns - 1, start models smoothed with a Gaussian of
     4 to 10 cells).  Pair k of a run: features at iterate k, target x_K - x_k
-    with K the run's last iterate."""
-    planes, scales, targets = [], [], []
-    stats = {"runs": 0, "evaluations": 0, "seconds": 0.0, "final_rel_misfit": []}
-    t0 = time.perf_counter()
+    with K the run's last iterate.
+
+    workers > 1 runs that many runs at a time, each host thread on its own
+    stream (default priority): a 128x128 gradient leaves the GPU mostly idle
+    between its launches.  Runs are independent and deterministic, and the
+    pairs are gathered in run order, so the dataset does not depend on
+    `workers`."""
+    from . import fwi
+    fwi.lib()
+    nn.lib()
     rng = np.random.default_rng(seed0)
-    for r in range(nruns):
-        cfg, prob, obs, e, s, e0, s0 = tiny_problem(seed0 + r, float(rng.uniform(4.0, 10.0)),
-                                                    device)
-        obj = Objective(prob, obs, e0, s0, st)
-        run = minimise(obj, iters, keep=True)
-        xK = run.xs[-1]
-        n = obj.ny * obj.nx
-        gsc = gradient_scales(obj, run.gs[0])
-        for xk, gk in zip(run.xs[:-1], run.gs[:-1]):
-            p, sc = feature_planes(obj, xk, gk, gsc)
-            planes.append(p)
-            scales.append(sc)
-            dx = (xK - xk).float()
-            targets.append(torch.stack([dx[:n], dx[n:]], dim=-1).view(obj.ny, obj.nx, 2))
-        stats["runs"] += 1
-        stats["evaluations"] += obj.evals
-        stats["final_rel_misfit"].append(run.log[-1].J / obj.J0)
-        if log and (r + 1) % max(1, nruns // 10) == 0:
-            log(f"generate: {r + 1}/{nruns} runs, {len(planes)} pairs, "
-                f"{time.perf_counter() - t0:.1f} s")
-    stats["seconds"] = time.perf_counter() - t0
-    stats["final_rel_misfit"] = float(np.mean(stats["final_rel_misfit"]))
+    smooth = [float(rng.uniform(4.0, 10.0)) for _ in range(nruns)]
+    results = [None] * nruns
+    t0 = time.perf_counter()
+    done = [0]
+
+    def note():
+        done[0] += 1
+        if log and done[0] % max(1, nruns // 10) == 0:
+            log(f"generate: {done[0]}/{nruns} runs, {time.perf_counter() - t0:.1f} s")
+
+    if workers <= 1:
+        for r in range(nruns):
+            results[r] = _one_run(r, seed0, iters, st, smooth[r], device)
+            note()
+    else:
+        import threading
+        lock = threading.Lock()
+        errors = []
+
+        def worker(w):
+            stream = torch.cuda.Stream(device=device)
+            try:
+                with torch.cuda.stream(stream):
+                    for r in range(w, nruns, workers):
+                        out = _one_run(r, seed0, iters, st, smooth[r], device)
+                        stream.synchronize()
+                        results[r] = out
+                        with lock:
+                            note()
+            except Exception as ex:       # reported after the join
+                errors.append(ex)
+
+        threads = [threading.Thread(target=worker, args=(w,)) for w in range(workers)]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
+        if errors:
+            raise errors[0]
+        torch.cuda.synchronize()
+    planes, scales, targets = [], [], []
+    evals, final = 0, []
+    for p, sc, tg, ne, fr in results:
+        planes += p
+        scales += sc
+        targets += tg
+        evals += ne
+        final.append(fr)
+    stats = {"runs": nruns, "evaluations": evals, "seconds": time.perf_counter() - t0,
+             "final_rel_misfit": float(np.mean(final)), "workers": workers}
     return Dataset(torch.stack(planes), torch.stack(scales), torch.stack(targets)), stats
 
 
@@ -566,6 +619,8 @@ def _summary(res):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--runs", type=int, default=667)
+    ap.add_argument("--workers", type=int, default=8,
+                    help="runs generated at a time, one host thread and stream each")
     ap.add_argument("--iters", type=int, default=30)
     ap.add_argument("--epochs", type=int, default=10)
     ap.add_argument("--batch", type=int, default=32)
@@ -593,7 +648,7 @@ def main(argv=None):
         net = nn.Net(np.load(args.load, allow_pickle=False))
         out["params"] = args.load
     else:
-        ds, gstats = generate(args.runs, args.iters, 10000, st, log=err)
+        ds, gstats = generate(args.runs, args.iters, 10000, st, log=err, workers=args.workers)
         err(f"generate: {gstats}")
         net, thist = train(ds, args.epochs, args.batch, args.lr, log=err)
         if args.save:

@@ -79,3 +79,21 @@ def test_problem_rejects_host_tensors():
     grid = fwi.make_grid(10, 10, 2, 20, 0.01, 0.01, 1e-11)
     with pytest.raises(ValueError):
         AG.Problem(grid, np.array([[5, 5]]), np.array([[[6, 6]]]), np.zeros((1, 20)), device="cpu")
+
+
+def test_pad_interior_gradient_equals_replicate_pad_adjoint():
+    """The explicit adjoint of the edge replication equals autograd through
+    torch's replicate padding (float64, CPU), including the corners."""
+    import torch
+    import torch.nn.functional as F
+    from paper_2506_20513_amd import fwi_loop as L
+    g = torch.Generator().manual_seed(3)
+    x = torch.randn(7, 9, generator=g, dtype=torch.float64, requires_grad=True)
+    w = torch.randn(7 + 6, 9 + 6, generator=g, dtype=torch.float64)
+    (L.pad_interior(x, 3) * w).sum().backward()
+    ours = x.grad.clone()
+    x.grad = None
+    (F.pad(x[None, None], (3, 3, 3, 3), mode="replicate")[0, 0] * w).sum().backward()
+    assert torch.allclose(ours, x.grad, rtol=1e-13, atol=1e-13)
+    assert torch.equal(L.pad_interior(x, 3).detach(),
+                       F.pad(x[None, None], (3, 3, 3, 3), mode="replicate")[0, 0].detach())

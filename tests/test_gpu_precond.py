@@ -24,6 +24,11 @@ def test_pairs_training_and_learned_inversion():
     ds, stats = PC.generate(2, 4, 10000, st, log=lambda m: print(m, flush=True))
     print("generate", stats, flush=True)
     assert ds.planes.shape == (8, 4, 128, 128) and ds.targets.shape == (8, 128, 128, 2)
+    # two runs at a time, each on its own stream: the same pairs bit for bit
+    ds2, stats2 = PC.generate(2, 4, 10000, st, log=None, workers=2)
+    assert stats2["workers"] == 2
+    for a, b in ((ds.planes, ds2.planes), (ds.scales, ds2.scales), (ds.targets, ds2.targets)):
+        assert torch.equal(a, b)
     assert torch.isfinite(ds.planes).all() and torch.isfinite(ds.targets).all()
     # the last pair of a run is one step: its target is that step, nonzero
     assert float(ds.targets[3].abs().max()) > 0
