@@ -233,76 +233,134 @@ __global__ void k_flip(const bf16 *__restrict__ w, bf16 *__restrict__ wf, int Ci
 }
 
 // ---------------------------------------------------------------------------
-// Weight and bias gradients: dw[co][ky][kx][ci] = sum_p dz[p][co] x[p + (ky-1, kx-1)][ci],
-// db[co] = sum_p dz[p][co].  GEMM with the pixels as reduction: a block owns
-// a 32 (co) x 32 (ci) tile for all nine taps, loops over every gridDim.x-th
-// chunk of 32 pixels and writes its partial sums to part[blockIdx.x].  Each
-// chunk's dz tile and its nine tap-shifted x tiles go through LDS transposed
-// (pixels contiguous per channel); every wave then issues nine matrix
-// instructions per chunk, one per tap, on its 16 x 16 sub-tile.
-constexpr int kPitch = 40;   // LDS row: 32 pixels + 8 padding (80 bytes, 16-byte aligned)
+// Weight and bias gradients: dw[co][ky][kx][ci] = sum_q dz[q][co] x[q + (ky-1, kx-1)][ci],
+// db[co] = sum_q dz[q][co].  A GEMM whose reduction runs over output pixels
+// q: a block owns a 32 (co) x 32 (ci) tile for all nine taps, loops over
+// every gridDim.x-th chunk of 32 pixels and writes its partial sums to
+// part[blockIdx.x].
+//
+// Per chunk q0 .. q0+31 the block stages, in natural (pixel-major) layout:
+//   Z[j][c]      = dz[q0 + j][co tile]                          (32 rows)
+//   X[ky][j][c]  = x[q0 - 1 + j + (ky-1) W][ci tile]             (34 rows)
+// X rows are zero where the row of q = q0 - 1 + j plus ky - 1 leaves the
+// image (or q is outside 0 .. P-1).  A tap (ky, kx) reads X[ky] from row kx
+// on, so the three kx taps share one staged tile; the taps that would wrap
+// across a row edge (kx = 0 at column 0, kx = 2 at column W-1) are removed
+// by zeroing those pixels in the dz fragment, in registers.
+//
+// The matrix fragments need 8 consecutive pixels of one channel per lane, a
+// column of the pixel-major tiles: each comes from two transposing LDS
+// reads (ds_read_b64_tr_b16).  Within a group of 16 lanes, lane i receives
+// element i % 4 of the 8-byte chunks read by lanes i/4, i/4+4, i/4+8 and
+// i/4+12; so with lane s of the group reading row base + s/4 at channel
+// 4 (s % 4), lane i gets channel i at rows base .. base + 3.
+constexpr int kWP = 40;     // LDS row pitch in bf16: 32 channels + 8 padding
+
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+typedef __attribute__((address_space(3))) bf16x4 *lds_bf16x4_ptr;
+
+// channels [16 h, 16 h + 16) of rows base .. base + 7 of a pixel-major LDS
+// tile, as this lane's 8-pixel fragment
+__device__ __forceinline__ bf16x8 tr_fragment(const bf16 *tile, int base, int h, int lane) {
+    const int s = lane & 15;
+    const bf16 *p0 = tile + (base + (s >> 2)) * kWP + 16 * h + 4 * (s & 3);
+    const bf16 *p1 = p0 + 4 * kWP;
+    const bf16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4_ptr)(p0));
+    const bf16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4_ptr)(p1));
+    return bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+}
 
 __global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ x,
                                                const bf16 *__restrict__ dz,
                                                float *__restrict__ part,
                                                float *__restrict__ bpart, int N, int H, int W,
                                                int Ci, int Co) {
-    __shared__ __attribute__((aligned(16))) bf16 zt[32][kPitch];      // [co][px]
-    __shared__ __attribute__((aligned(16))) bf16 xt[9][32][kPitch];   // [tap][ci][px]
+    __shared__ __attribute__((aligned(16))) bf16 Z[32 * kWP];
+    __shared__ __attribute__((aligned(16))) bf16 X[3][34 * kWP];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = threadIdx.x;
     const int nci = Ci / 32;
     const int cit = blockIdx.y % nci, cot = blockIdx.y / nci;
     const int64_t P = (int64_t)N * H * W;
     const int64_t nchunk = (P + 31) / 32;
-    const int mt = wave >> 1, nt = wave & 1;      // this wave's 16x16 sub-tile
+    const int mt = wave >> 1, nt = wave & 1;      // this wave's 16 x 16 sub-tile
+    const int g = lane >> 4;                      // pixel group: rows 8 g .. 8 g + 7
     f32x4 acc[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
     float bsum = 0.f;                               // bias partial (ci tile 0)
     const bool do_bias = cit == 0;
-    // fill role: pixel fp = t >> 3, channels fc .. fc+3 (8 bytes)
-    const int fp = t >> 3, fc = (t & 7) * 4;
-    for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
-        const int64_t p = ch * 32 + fp;
-        uint2 zv = make_uint2(0u, 0u);
-        uint2 xv[9];
+    const bf16 zero = (bf16)0.f;
+    // staging: 32 x 4 pieces of Z, then 3 x 34 x 4 pieces of X (16 bytes
+    // each), at most three per thread; the pieces of the next chunk are
+    // loaded into registers while the current chunk computes
+    constexpr int kPieces = 32 * 4 + 3 * 34 * 4;
+    uint4 pre[3];
+    auto fetch = [&](int64_t q0, uint4 *out) {
+        const int col0 = (int)(q0 % W), row0 = (int)((q0 / W) % H);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) xv[k] = make_uint2(0u, 0u);
-        if (p < P) {
-            zv = *reinterpret_cast<const uint2 *>(dz + p * Co + cot * 32 + fc);
-            const int px = (int)(p % W), py = (int)((p / W) % H);
-#pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                const int xx = px + k % 3 - 1, yy = py + k / 3 - 1;
-                if (xx >= 0 && xx < W && yy >= 0 && yy < H)
-                    xv[k] = *reinterpret_cast<const uint2 *>(
-                        x + (p + (int64_t)(k / 3 - 1) * W + (k % 3 - 1)) * Ci + cit * 32 + fc);
+        for (int u = 0; u < 3; ++u) {
+            const int idx = t + 256 * u;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (idx < 128) {
+                const int j = idx >> 2, c = (idx & 3) * 8;
+                const int64_t q = q0 + j;
+                if (q < P) v = *reinterpret_cast<const uint4 *>(dz + q * Co + cot * 32 + c);
+            } else if (idx < kPieces) {
+                const int r = idx - 128;
+                const int ky = r / (34 * 4), j = (r >> 2) % 34, c = (r & 3) * 8;
+                const int64_t q = q0 - 1 + j;
+                if (q >= 0 && q < P) {
+                    const int d = col0 - 1 + j;                 // >= -1
+                    const int row = row0 + (d >= 0 ? d / W : -1);
+                    const int yy = (row % H + H) % H + ky - 1;
+                    if (yy >= 0 && yy < H)
+                        v = *reinterpret_cast<const uint4 *>(
+                            x + (q + (int64_t)(ky - 1) * W) * Ci + cit * 32 + c);
+                }
             }
+            out[u] = v;
         }
+    };
+    if ((int64_t)blockIdx.x < nchunk) fetch((int64_t)blockIdx.x * 32, pre);
+    for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+        const int64_t q0 = ch * 32;
+        const int col0 = (int)(q0 % W);
         __syncthreads();   // previous chunk's reads done
-        {
-            const bf16 *zb = reinterpret_cast<const bf16 *>(&zv);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) zt[fc + i][fp] = zb[i];
-#pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                const bf16 *xb = reinterpret_cast<const bf16 *>(&xv[k]);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) xt[k][fc + i][fp] = xb[i];
+        for (int u = 0; u < 3; ++u) {
+            const int idx = t + 256 * u;
+            if (idx < 128) {
+                *reinterpret_cast<uint4 *>(&Z[(idx >> 2) * kWP + (idx & 3) * 8]) = pre[u];
+            } else if (idx < kPieces) {
+                const int r = idx - 128;
+                *reinterpret_cast<uint4 *>(&X[r / (34 * 4)][((r >> 2) % 34) * kWP + (r & 3) * 8]) =
+                    pre[u];
             }
         }
         __syncthreads();
-        const bf16x8 a =
-            *reinterpret_cast<const bf16x8 *>(&zt[16 * mt + (lane & 15)][8 * (lane >> 4)]);
+        if (ch + gridDim.x < nchunk) fetch((ch + gridDim.x) * 32, pre);
+        // dz fragment (channels 16 mt .. +15, pixels 8 g .. 8 g + 7) and its
+        // two edge-masked copies
+        const bf16x8 a1 = tr_fragment(Z, 8 * g, mt, lane);
+        bf16x8 a0 = a1, a2 = a1;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            const bf16x8 bv =
-                *reinterpret_cast<const bf16x8 *>(&xt[k][16 * nt + (lane & 15)][8 * (lane >> 4)]);
-            acc[k] = mfma(a, bv, acc[k]);
+        for (int e = 0; e < 8; ++e) {
+            const int col = (col0 + 8 * g + e) % W;
+            if (col == 0) a0[e] = zero;
+            if (col == W - 1) a2[e] = zero;
+        }
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky) {
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {
+                const bf16x8 bv = tr_fragment(X[ky], 8 * g + kx, nt, lane);
+                const bf16x8 a = kx == 0 ? a0 : (kx == 1 ? a1 : a2);
+                acc[ky * 3 + kx] = mfma(a, bv, acc[ky * 3 + kx]);
+            }
         }
         if (do_bias && t < 32) {
 #pragma unroll 8
-            for (int q = 0; q < 32; ++q) bsum += (float)zt[t][q];
+            for (int j = 0; j < 32; ++j) bsum += (float)Z[j * kWP + t];
         }
     }
     // partial tile of this block

@@ -88,10 +88,14 @@ def test_flipped_conv_is_the_input_gradient():
     _close_bf16(dx.view(N, H, W, Ci), x.grad, aref, "input gradient")
 
 
-@pytest.mark.parametrize("nsplit", [1, 3, 700])
-def test_weight_gradient_matches_reference(nsplit):
+@pytest.mark.parametrize("N,H,W,Ci,Co,nsplit", [(2, 10, 37, 32, 64, 1), (2, 10, 37, 32, 64, 3),
+                                                 (2, 10, 37, 32, 64, 700),
+                                                 # chunks crossing rows and images, odd width
+                                                 (3, 7, 13, 32, 64, 5),
+                                                 # several channel tiles both ways
+                                                 (2, 9, 21, 64, 96, 2), (1, 1, 1, 32, 32, 1)])
+def test_weight_gradient_matches_reference(N, H, W, Ci, Co, nsplit):
     import torch
-    N, H, W, Ci, Co = 2, 10, 37, 32, 64
     x = _bf((N, H, W, Ci), 7)
     w = _bf((Co, 3, 3, Ci), 8, 0.1).double().requires_grad_(True)
     g = _bf((N, H, W, Co), 9)
