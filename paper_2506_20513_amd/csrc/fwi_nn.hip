@@ -111,41 +111,17 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ x,
 }
 
 // The same convolution with both operand tiles staged in LDS: a block
-// computes 128 consecutive (flattened) pixels x BN output channels.  Each
-// reduction step (one tap, 32 input channels) copies the 128 x 32 input tile
-// (zeros outside the image) and the BN x 32 weight tile into one of two LDS
-// buffers; the global loads of step k+1 are issued before the matrix
-// instructions of step k, and one barrier per step separates the buffers.
-// Wave w computes pixels [32 w, 32 w + 32) x all BN channels: 2 x BN/16
-// MFMAs per step from LDS fragments.
+// computes 128 consecutive (flattened) pixels x BN output channels.  A
+// reduction step covers one kernel row ky and 32 input channels for all
+// three kx taps: it stages the input rows of pixels base - 1 .. base + 128
+// shifted by ky - 1 image rows (130 rows, zero where that row leaves the
+// image) and the three BN x 32 weight tiles of (ky, kx = 0, 1, 2).  Tap kx
+// of output pixel p reads staged row p - base + kx, so the three taps share
+// the staged rows; a tap that would wrap across a row edge (kx = 0 at column
+// 0, kx = 2 at column W-1) gets a zero fragment.  Two LDS buffers, one
+// barrier per step; the global loads of step k+1 are in flight while step k
+// issues its 3 x 2 x BN/16 MFMAs per wave.
 constexpr int kTP = 40;      // LDS row pitch in bf16: 32 channels + 8 padding (80 bytes)
-
-struct Stage {
-    uint4 a0, a1, b;             // 16 input channels (two pieces) and 8 weight channels
-};
-
-// global loads of reduction step k for one thread's copy roles
-__device__ __forceinline__ Stage conv_gload(const bf16 *__restrict__ x, const bf16 *__restrict__ w,
-                                            int k, int nck, int Ci, int H, int W, bool pvA,
-                                            int64_t ppA, int pyA, int pxA, int ah, bool bact,
-                                            int co0, int bco, int bq) {
-    Stage s;
-    const int tap = k / nck, c0 = (k - tap * nck) * 32;
-    const int ky = tap / 3, kx = tap - ky * 3;
-    const int yy = pyA + ky - 1, xx = pxA + kx - 1;
-    if (pvA && yy >= 0 && yy < H && xx >= 0 && xx < W) {
-        const bf16 *src = x + (ppA + (int64_t)(ky - 1) * W + (kx - 1)) * Ci + c0 + ah;
-        s.a0 = *reinterpret_cast<const uint4 *>(src);
-        s.a1 = *reinterpret_cast<const uint4 *>(src + 8);
-    } else {
-        s.a0 = make_uint4(0u, 0u, 0u, 0u);
-        s.a1 = s.a0;
-    }
-    s.b = make_uint4(0u, 0u, 0u, 0u);
-    if (bact)
-        s.b = *reinterpret_cast<const uint4 *>(w + ((size_t)(co0 + bco) * 9 + tap) * Ci + c0 + bq);
-    return s;
-}
 
 template <int BN>
 __global__ __launch_bounds__(256) void k_conv3x3_lds(const bf16 *__restrict__ x,
@@ -153,54 +129,102 @@ __global__ __launch_bounds__(256) void k_conv3x3_lds(const bf16 *__restrict__ x,
                                                      const float *__restrict__ bias,
                                                      bf16 *__restrict__ y, int N, int H, int W,
                                                      int Ci, int Co, int relu) {
-    constexpr int BM = 128, NTL = BN / 16;
-    __shared__ __attribute__((aligned(16))) bf16 As[2][BM][kTP];
-    __shared__ __attribute__((aligned(16))) bf16 Bs[2][BN][kTP];
+    constexpr int BM = 128, AR = BM + 2, NTL = BN / 16;
+    constexpr int APieces = AR * 4, BPieces = 3 * BN * 4;     // 16-byte pieces per step
+    constexpr int AU = (APieces + 255) / 256, BU = (BPieces + 255) / 256;
+    __shared__ __attribute__((aligned(16))) bf16 As[2][AR * kTP];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[2][3 * BN * kTP];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t P = (int64_t)N * H * W;
     const int64_t base = (int64_t)blockIdx.x * BM;
     const int co0 = blockIdx.y * BN;
-    // copy roles: input pixel ap (two threads per pixel, 16 channels each);
-    // weight row bco (four threads per row, 8 channels each)
-    const int ap = t >> 1, ah = (t & 1) * 16;
-    const int64_t pA = base + ap;
-    const bool pvA = pA < P;
-    const int64_t ppA = pvA ? pA : 0;
-    const int pxA = (int)(ppA % W), pyA = (int)((ppA / W) % H);
-    const int bco = t >> 2, bq = (t & 3) * 8;
-    const bool bact = bco < BN;
-    const int nck = Ci / 32, K = 9 * nck;
+    const int col0 = (int)(base % W), row0 = (int)((base / W) % H);
+    const int nck = Ci / 32, K = 3 * nck;
+    // this lane's output pixels (offsets in the block) and their columns
+    int pofs[2], pcol[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        pofs[m] = wave * 32 + m * 16 + (lane & 15);
+        pcol[m] = (col0 + pofs[m]) % W;
+    }
+    uint4 ra[AU], rb[BU];
+    auto fetch = [&](int k) {
+        const int ky = k / nck, c0 = (k - ky * nck) * 32;
+#pragma unroll
+        for (int u = 0; u < AU; ++u) {
+            const int idx = t + 256 * u;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (idx < APieces) {
+                const int j = idx >> 2, c = (idx & 3) * 8;
+                const int64_t q = base - 1 + j;
+                if (q >= 0 && q < P) {
+                    const int d = col0 - 1 + j;                 // >= -1
+                    const int row = row0 + (d >= 0 ? d / W : -1);
+                    const int yy = (row % H + H) % H + ky - 1;
+                    if (yy >= 0 && yy < H)
+                        v = *reinterpret_cast<const uint4 *>(
+                            x + (q + (int64_t)(ky - 1) * W) * Ci + c0 + c);
+                }
+            }
+            ra[u] = v;
+        }
+#pragma unroll
+        for (int u = 0; u < BU; ++u) {
+            const int idx = t + 256 * u;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (idx < BPieces) {
+                const int kx = idx / (BN * 4), r = idx - kx * (BN * 4);
+                const int n = r >> 2, c = (r & 3) * 8;
+                v = *reinterpret_cast<const uint4 *>(
+                    w + ((size_t)(co0 + n) * 9 + ky * 3 + kx) * Ci + c0 + c);
+            }
+            rb[u] = v;
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < AU; ++u) {
+            const int idx = t + 256 * u;
+            if (idx < APieces)
+                *reinterpret_cast<uint4 *>(&As[buf][(idx >> 2) * kTP + (idx & 3) * 8]) = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < BU; ++u) {
+            const int idx = t + 256 * u;
+            if (idx < BPieces)
+                *reinterpret_cast<uint4 *>(&Bs[buf][(idx >> 2) * kTP + (idx & 3) * 8]) = rb[u];
+        }
+    };
     f32x4 acc[2][NTL];
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
         for (int n = 0; n < NTL; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-    Stage st = conv_gload(x, w, 0, nck, Ci, H, W, pvA, ppA, pyA, pxA, ah, bact, co0, bco, bq);
-    *reinterpret_cast<uint4 *>(&As[0][ap][ah]) = st.a0;
-    *reinterpret_cast<uint4 *>(&As[0][ap][ah + 8]) = st.a1;
-    if (bact) *reinterpret_cast<uint4 *>(&Bs[0][bco][bq]) = st.b;
+    const bf16x8 zero{};
+    fetch(0);
+    stash(0);
     __syncthreads();
     for (int k = 0; k < K; ++k) {
         const int buf = k & 1;
-        if (k + 1 < K)
-            st = conv_gload(x, w, k + 1, nck, Ci, H, W, pvA, ppA, pyA, pxA, ah, bact, co0, bco, bq);
-        bf16x8 a[2];
+        if (k + 1 < K) fetch(k + 1);
 #pragma unroll
-        for (int m = 0; m < 2; ++m)
-            a[m] = *reinterpret_cast<const bf16x8 *>(
-                &As[buf][wave * 32 + m * 16 + (lane & 15)][8 * (lane >> 4)]);
+        for (int kx = 0; kx < 3; ++kx) {
+            bf16x8 a[2];
 #pragma unroll
-        for (int n = 0; n < NTL; ++n) {
-            const bf16x8 bv =
-                *reinterpret_cast<const bf16x8 *>(&Bs[buf][n * 16 + (lane & 15)][8 * (lane >> 4)]);
+            for (int m = 0; m < 2; ++m) {
+                a[m] = *reinterpret_cast<const bf16x8 *>(
+                    &As[buf][(pofs[m] + kx) * kTP + 8 * (lane >> 4)]);
+                if ((kx == 0 && pcol[m] == 0) || (kx == 2 && pcol[m] == W - 1)) a[m] = zero;
+            }
 #pragma unroll
-            for (int m = 0; m < 2; ++m) acc[m][n] = mfma(a[m], bv, acc[m][n]);
+            for (int n = 0; n < NTL; ++n) {
+                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(
+                    &Bs[buf][(kx * BN + n * 16 + (lane & 15)) * kTP + 8 * (lane >> 4)]);
+#pragma unroll
+                for (int m = 0; m < 2; ++m) acc[m][n] = mfma(a[m], bv, acc[m][n]);
+            }
         }
-        if (k + 1 < K) {
-            *reinterpret_cast<uint4 *>(&As[buf ^ 1][ap][ah]) = st.a0;
-            *reinterpret_cast<uint4 *>(&As[buf ^ 1][ap][ah + 8]) = st.a1;
-            if (bact) *reinterpret_cast<uint4 *>(&Bs[buf ^ 1][bco][bq]) = st.b;
-        }
+        if (k + 1 < K) stash(buf ^ 1);
         __syncthreads();
     }
 #pragma unroll
