@@ -16,9 +16,10 @@ inversion.
    lengths (the first one carried over from the previous proposal's
    quadratic fit, so an accepted proposal usually costs one evaluation).
    Otherwise the plain L-BFGS step is taken.  Both kinds of steps feed the
-   same L-BFGS curvature memory.  A proposal whose first trial
-   length fails is a strike; after two strikes in a row the run continues as
-   plain L-BFGS.
+   same L-BFGS curvature memory.  A proposal whose first trial length fails,
+   or whose decrease falls short of what the L-BFGS step's quadratic model
+   predicts for itself, is a strike; after two strikes in a row the run
+   continues as plain L-BFGS.
 
 Network input at iterate k: the two gradient planes divided by the rms of
 the run's first gradient (so the input shows how far the gradient has
@@ -222,10 +223,12 @@ def minimise(obj: Objective, iters: int, history: int = 10, first_step: float = 
     target_f).  proposer(x, g) -> direction or None is tried first at every
     iterate (proposal_search: at most two evaluations, starting from the
     length the previous proposal's quadratic fit suggested); the decrease it
-    achieves decides, otherwise the L-BFGS step is taken.  A proposal whose
-    first trial length does not pass is a strike (even if the second one
-    does); after max_strikes strikes in a row the proposer is no longer
-    asked and the run continues as plain L-BFGS.  keep: retain
+    achieves decides, otherwise the L-BFGS step is taken.  A proposal is a
+    strike when its first trial length does not pass (even if the second
+    one does), or when it decreases the objective by less than the L-BFGS
+    step's own quadratic model predicts (-g.d_L / 2, once L-BFGS holds
+    curvature pairs); after max_strikes strikes in a row the proposer is no
+    longer asked and the run continues as plain L-BFGS.  keep: retain
     iterates and gradients (for training pairs)."""
     torch.cuda.synchronize() if obj.x0.is_cuda else None
     t0 = time.perf_counter()
@@ -258,9 +261,15 @@ def minimise(obj: Objective, iters: int, history: int = 10, first_step: float = 
             if d is not None:
                 res, t_net = proposal_search(obj, x, f, g, d, t0=t_net)
                 passed = getattr(obj, "first_trial_passed", False)
+                dl = mem.direction(g)
+                if res is not None and passed and dl is not None:
+                    # the L-BFGS step's own quadratic model predicts a decrease
+                    # of -g.d/2; a proposal that does worse is kept (it is paid
+                    # for) but does not earn another try
+                    passed = f - res[1] >= -0.5 * float(torch.dot(g, dl))
             src = "net"
-            # a proposal that needed its second trial length (or failed) costs
-            # more evaluations than an L-BFGS step usually does: a strike
+            # a proposal that needed its second trial length, failed, or fell
+            # short of the L-BFGS prediction is a strike
             strikes = 0 if passed else strikes + 1
         if res is None:
             d = mem.direction(g)
