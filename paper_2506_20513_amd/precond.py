@@ -30,7 +30,7 @@ Units: the optimiser works on the interior models normalised as in fwi_loop
 The rows just below the surface stay fixed, and every iterate is projected
 onto eps_r >= eps_min, sigma >= sig_min.
 
-    python -m paper_2506_20513_amd.precond --runs 667 --iters 30 --epochs 10 --survey
+    python -m paper_2506_20513_amd.precond --runs 667 --iters 30 --epochs 30 --survey
 """
 from __future__ import annotations
 
@@ -631,7 +631,7 @@ def main(argv=None):
     ap.add_argument("--workers", type=int, default=8,
                     help="runs generated at a time, one host thread and stream each")
     ap.add_argument("--iters", type=int, default=30)
-    ap.add_argument("--epochs", type=int, default=10)
+    ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--eval", type=int, default=8, help="held-out 128x128 problems")
