@@ -272,7 +272,15 @@ def param_count():
 class Net:
     """Parameters, optimiser state and activation buffers of the network on
     one device.  forward() / backward() / adam_step() enqueue kernels on the
-    current stream; buffers are (re)allocated when the batch shape changes."""
+    current stream; buffers are (re)allocated when the batch shape changes.
+
+    The weight gradient of a layer splits its pixel sum over nsplit blocks
+    per channel tile: about WGRAD_BLOCKS blocks in all, at most
+    WGRAD_MAX_SPLIT partial sums (each is a full weight tensor for the
+    reduction to read)."""
+
+    WGRAD_BLOCKS = 1024
+    WGRAD_MAX_SPLIT = 512
 
     def __init__(self, params: np.ndarray | torch.Tensor | None = None, seed: int = 0,
                  device="cuda", out_scale: float = 0.0):
@@ -348,7 +356,8 @@ class Net:
             h, w = hw[lv]
             chunks = (N * h * w + 31) // 32
             tiles = (co // 32) * (ci // 32)
-            ns = int(max(1, min(chunks, (2048 + tiles - 1) // tiles, 512)))
+            ns = int(max(1, min(chunks, (self.WGRAD_BLOCKS + tiles - 1) // tiles,
+                                self.WGRAD_MAX_SPLIT)))
             self.nsplit.append(ns)
             wsb = max(wsb, wgrad_workspace(ci, co, ns))
         self.wsg = torch.empty((wsb + 3) // 4, dtype=F32, device=dev)
