@@ -57,8 +57,10 @@ def _close_bf16(got, ref, absref, what):
 
 @pytest.mark.parametrize("N,H,W,Ci,Co,relu", [(2, 13, 70, 32, 64, 1), (1, 9, 130, 64, 96, 0),
                                               (3, 5, 17, 96, 32, 1), (1, 1, 1, 32, 32, 0),
-                                              # two 16-pixel tiles per wave, ragged last block
-                                              (8, 61, 67, 32, 256, 1), (16, 61, 67, 32, 96, 0)])
+                                              # LDS-tiled kernel: 4 pixel tiles per wave
+                                              # (64 channels), 2 per wave (64 and 32 channels)
+                                              (8, 61, 67, 32, 256, 1), (4, 64, 64, 32, 128, 1),
+                                              (16, 61, 67, 32, 96, 0)])
 def test_conv3x3_matches_reference(N, H, W, Ci, Co, relu):
     import torch
     x = _bf((N, H, W, Ci), 1)
