@@ -5,11 +5,14 @@ misfit Eq. (6) with the adjoint gradients Eqs. (12)-(13) of Sec. 2.1).
 The paper has no learned component; this module adds one on top of its
 inversion.
 
-1. Plain L-BFGS FWI runs on seeded 128x128 models generate pairs.  Each pair
+1. Plain L-BFGS FWI runs on seeded 128x128 models, and on seeded 512x256
+   layered models with the survey acquisition, generate pairs.  Each pair
    maps the state at iterate k (grad_eps, grad_sigma, eps_r, sigma) to the
    update the run makes from there to its final iterate K.
 2. The encoder-decoder CNN of `nn` (BF16 MFMA kernels, FP32 accumulation)
-   is trained on those pairs with Adam.
+   is trained on both sets of pairs with Adam.  On a model whose cells are
+   finer per wavelength than the training models', it is applied to the
+   gradient pooled to the training resolution and its output upsampled.
 3. Inside an inversion, the network proposes a step at every iterate.  The
    objective decrease judges the proposal: it needs a descent direction and
    at least a tenth of the decrease its slope predicts, within two trial
@@ -30,7 +33,7 @@ Units: the optimiser works on the interior models normalised as in fwi_loop
 The rows just below the surface stay fixed, and every iterate is projected
 onto eps_r >= eps_min, sigma >= sig_min.
 
-    python -m paper_2506_20513_amd.precond --runs 667 --iters 30 --epochs 30 --survey
+    python -m paper_2506_20513_amd.precond --runs 667 --survey-runs 96 --epochs 30 --survey --large
 """
 from __future__ import annotations
 
@@ -415,10 +418,33 @@ def tiny_problem(seed: int, smoothing: float, device="cuda"):
     return cfg, prob, obs, T(e), T(s), T(e0), T(s0)
 
 
-def _one_run(r: int, seed0: int, iters: int, st: FL.Settings, smoothing: float, device):
+def survey_problem(seed: int, smoothing: float, device="cuda"):
+    """A seeded 512x256 layered model with the survey acquisition (24 shots x
+    128 receivers, 400 MHz, dx = 0.01 m): true model, start smoothed with a
+    Gaussian of `smoothing` cells, observed traces, and the autograd
+    problem."""
+    from . import fwi
+    from . import inputs as I
+    cfg = I.config_survey()
+    e, s = I.model_layered(cfg, seed)
+    e0, s0 = I.smooth_model(e, s, cfg.npml, smoothing)
+    src, rec = I.geometry(cfg)
+    w = torch.from_numpy(I.wavelets(cfg).copy()).to(device)
+    prob = AG.Problem(fwi.grid_from_config(cfg), src, rec, w, device=device)
+    T = lambda a: torch.from_numpy(a).to(device)
+    with torch.no_grad():
+        obs = AG.traces(prob, T(e), T(s))
+    return cfg, prob, obs, T(e), T(s), T(e0), T(s0)
+
+
+def _one_run(r: int, seed0: int, iters: int, st: FL.Settings, smoothing: float, device,
+             kind: str = "tiny"):
     """Pairs of plain run r: features at every iterate but the last, and the
     update from there to the last iterate."""
-    cfg, prob, obs, e, s, e0, s0 = tiny_problem(seed0 + r, smoothing, device)
+    if kind == "tiny":
+        cfg, prob, obs, e, s, e0, s0 = tiny_problem(seed0 + r, smoothing, device)
+    else:
+        cfg, prob, obs, e, s, e0, s0 = survey_problem(seed0 + r, 2.0 * smoothing, device)
     obj = Objective(prob, obs, e0, s0, st)
     run = minimise(obj, iters, keep=True)
     xK = run.xs[-1]
@@ -435,7 +461,7 @@ def _one_run(r: int, seed0: int, iters: int, st: FL.Settings, smoothing: float, 
 
 
 def generate(nruns: int, iters: int, seed0: int, st: FL.Settings, log=print,
-             device="cuda", workers: int = 1) -> tuple[Dataset, dict]:
+             device="cuda", workers: int = 1, kind: str = "tiny") -> tuple[Dataset, dict]:
     """Pairs from nruns plain L-BFGS runs on seeded 128x128 models (seeds
     seed0 .. seed0 + nruns - 1, start models smoothed with a Gaussian of
     4 to 10 cells).  Pair k of a run: features at iterate k, target x_K - x_k
@@ -445,7 +471,10 @@ def generate(nruns: int, iters: int, seed0: int, st: FL.Settings, log=print,
     stream (default priority): a 128x128 gradient leaves the GPU mostly idle
     between its launches.  Runs are independent and deterministic, and the
     pairs are gathered in run order, so the dataset does not depend on
-    `workers`."""
+    `workers`.  kind = "survey" takes seeded 512x256 layered models with the
+    survey acquisition instead, starts smoothed over 8 to 20 cells (the
+    survey workload's start is smoothed over 10 cells; the 2048x1024 model's
+    over 40, i.e. 20 once resampled by 2 to the survey's cell size)."""
     from . import fwi
     fwi.lib()
     nn.lib()
@@ -462,7 +491,7 @@ def generate(nruns: int, iters: int, seed0: int, st: FL.Settings, log=print,
 
     if workers <= 1:
         for r in range(nruns):
-            results[r] = _one_run(r, seed0, iters, st, smooth[r], device)
+            results[r] = _one_run(r, seed0, iters, st, smooth[r], device, kind)
             note()
     else:
         import threading
@@ -474,7 +503,7 @@ def generate(nruns: int, iters: int, seed0: int, st: FL.Settings, log=print,
             try:
                 with torch.cuda.stream(stream):
                     for r in range(w, nruns, workers):
-                        out = _one_run(r, seed0, iters, st, smooth[r], device)
+                        out = _one_run(r, seed0, iters, st, smooth[r], device, kind)
                         stream.synchronize()
                         results[r] = out
                         with lock:
@@ -522,39 +551,63 @@ def mean_loss(net: nn.Net, ds: Dataset, ids, batch: int = 32) -> float:
     return tot / max(ids.numel(), 1)
 
 
-def train(ds: Dataset, epochs: int, batch: int = 32, lr: float = 1e-3, seed: int = 0,
+def train(ds, epochs: int, batch: int = 32, lr: float = 1e-3, seed: int = 0,
           val_frac: float = 0.05, warmup: int = 100, log=print, device="cuda") -> tuple[nn.Net, dict]:
     """Adam on the mean squared error between network output and target:
     linear warm-up over `warmup` steps, then cosine decay to zero.  A
-    fraction val_frac of the pairs is held out for validation."""
-    M = len(ds)
+    fraction val_frac of the pairs is held out for validation.
+
+    ds: one Dataset or a list of them (images of different sizes).  Each
+    dataset is cut into batches of about `batch` x 128 x 128 pixels, and
+    every epoch visits all batches of all datasets in a seeded random
+    order."""
+    sets = ds if isinstance(ds, (list, tuple)) else [ds]
     g = torch.Generator().manual_seed(seed)
-    perm = torch.randperm(M, generator=g)
-    nval = int(M * val_frac)
-    val, tr = perm[:nval].to(device), perm[nval:].to(device)
-    H, W = ds.planes.shape[2], ds.planes.shape[3]
     net = nn.Net(seed=seed, device=device)
-    xin = torch.empty(batch * H * W * nn.CPAD, dtype=torch.bfloat16, device=device)
-    dy = torch.empty(batch * H * W * nn.CPAD, dtype=torch.bfloat16, device=device)
-    hist = {"epochs": [], "zero_predictor_val": None, "train_ids": tr, "val_ids": val}
-    if nval:
-        hist["zero_predictor_val"] = float((ds.targets[val].double() ** 2).mean())
+    parts = []
+    for d in sets:
+        M = len(d)
+        perm = torch.randperm(M, generator=g)
+        nval = int(M * val_frac)
+        H, W = d.planes.shape[2], d.planes.shape[3]
+        b = max(1, round(batch * 128 * 128 / (H * W)))
+        parts.append({"ds": d, "val": perm[:nval].to(device), "tr": perm[nval:].to(device),
+                      "batch": b, "H": H, "W": W,
+                      "xin": torch.empty(b * H * W * nn.CPAD, dtype=torch.bfloat16, device=device),
+                      "dy": torch.empty(b * H * W * nn.CPAD, dtype=torch.bfloat16, device=device)})
+    hist = {"epochs": [], "zero_predictor_val": None,
+            "train_ids": parts[0]["tr"], "val_ids": parts[0]["val"]}
+    nval_all = sum(p["val"].numel() for p in parts)
+    if nval_all:
+        hist["zero_predictor_val"] = float(sum(float((p["ds"].targets[p["val"]].double() ** 2).sum())
+                                               for p in parts if p["val"].numel())
+                                           / sum(p["val"].numel() * p["H"] * p["W"] * 2
+                                                 for p in parts))
     t0 = time.perf_counter()
     steps = 0
-    nb = tr.numel() // batch
-    total = max(1, epochs * nb)
+    per_epoch = sum(p["tr"].numel() // p["batch"] for p in parts)
+    total = max(1, epochs * per_epoch)
     warmup = min(warmup, max(1, total // 10))
     for ep in range(epochs):
-        order = tr[torch.randperm(tr.numel(), generator=g).to(device)]
-        losses = torch.zeros(max(nb, 1), dtype=torch.float64, device=device)
-        for i in range(nb):
-            idx = order[i * batch:(i + 1) * batch]
-            losses[i] = _batch_loss(net, ds, idx, xin, dy)[0]
-            net.backward(dy)
+        plan = []
+        for k, p in enumerate(parts):
+            order = p["tr"][torch.randperm(p["tr"].numel(), generator=g).to(device)]
+            nb = p["tr"].numel() // p["batch"]
+            plan += [(k, order[i * p["batch"]:(i + 1) * p["batch"]]) for i in range(nb)]
+        shuffle = torch.randperm(len(plan), generator=g).tolist()
+        losses = torch.zeros(max(len(plan), 1), dtype=torch.float64, device=device)
+        for i, j in enumerate(shuffle):
+            k, idx = plan[j]
+            p = parts[k]
+            losses[i] = _batch_loss(net, p["ds"], idx, p["xin"], p["dy"])[0]
+            net.backward(p["dy"])
             f = min(1.0, (steps + 1) / warmup) * 0.5 * (1.0 + math.cos(math.pi * steps / total))
             net.adam_step(lr * f)
             steps += 1
-        vl = mean_loss(net, ds, val, batch) if nval else float("nan")
+        vl = float("nan")
+        if nval_all:
+            vl = sum(mean_loss(net, p["ds"], p["val"], p["batch"]) * p["val"].numel()
+                     for p in parts if p["val"].numel()) / nval_all
         torch.cuda.synchronize()
         rec = {"epoch": ep + 1, "train_loss": float(losses.mean()), "val_loss": vl,
                "seconds": time.perf_counter() - t0}
@@ -640,10 +693,14 @@ def main(argv=None):
     ap.add_argument("--large", action="store_true", help="also compare on the 2048x1024 model")
     ap.add_argument("--large-iters", type=int, default=5)
     ap.add_argument("--save", default=None, help="write the trained parameters (.npy)")
-    ap.add_argument("--factor", type=int, default=1,
+    ap.add_argument("--factor", type=int, default=0,
                     help="resampling factor of the network on the survey and large models; 0 = "
-                         "matched to the training models' cells per wavelength (2 on the large "
-                         "model, where it measured slower than 1)")
+                         "matched to the training models' cells per wavelength (1 on the survey, "
+                         "2 on the large model)")
+    ap.add_argument("--survey-runs", type=int, default=96,
+                    help="also train on pairs from this many plain runs on seeded 512x256 "
+                         "layered models (seeds 20000 on; the survey comparison uses seed 2)")
+    ap.add_argument("--survey-pair-iters", type=int, default=10)
     ap.add_argument("--load", default=None,
                     help="trained parameters (.npy) to use instead of generating and training")
     args = ap.parse_args(argv)
@@ -659,13 +716,20 @@ def main(argv=None):
     else:
         ds, gstats = generate(args.runs, args.iters, 10000, st, log=err, workers=args.workers)
         err(f"generate: {gstats}")
-        net, thist = train(ds, args.epochs, args.batch, args.lr, log=err)
+        sets = [ds]
+        if args.survey_runs:
+            ds2, gs2 = generate(args.survey_runs, args.survey_pair_iters, 20000, st, log=err,
+                                workers=min(args.workers, 4), kind="survey")
+            err(f"generate survey: {gs2}")
+            out["generate_survey"] = gs2
+            sets.append(ds2)
+        net, thist = train(sets, args.epochs, args.batch, args.lr, log=err)
         if args.save:
             np.save(args.save, net.state_dict()["params"])
         out.update({"pairs": gstats["runs"] * args.iters, "generate": gstats,
                     "train": {k: thist[k] for k in ("steps", "seconds", "zero_predictor_val")},
                     "train_last": thist["epochs"][-1] if thist["epochs"] else None})
-        del ds
+        del ds, sets
         torch.cuda.empty_cache()
     problems = []
     for k in range(args.eval):

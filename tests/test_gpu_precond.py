@@ -65,3 +65,28 @@ def test_pairs_training_and_learned_inversion():
     assert float(d[~obj.free].abs().max()) == 0.0
     u = d[: obj.ny * obj.nx].view(obj.ny, obj.nx)[8:, :]
     assert torch.equal(u[0::2, 0::2], u[1::2, 1::2])
+
+
+def test_survey_pairs_and_training_over_two_image_sizes():
+    import math
+
+    import torch
+    from paper_2506_20513_amd import fwi_loop as FL
+    from paper_2506_20513_amd import precond as PC
+    st = FL.Settings(tv_weight=1e-3)
+    tiny, _ = PC.generate(2, 4, 10000, st, log=None)
+    big, stats = PC.generate(1, 2, 20000, st, log=lambda m: print(m, flush=True), kind="survey")
+    print("generate survey", stats, flush=True)
+    assert big.planes.shape == (2, 4, 256, 512) and big.targets.shape == (2, 256, 512, 2)
+    assert torch.isfinite(big.planes).all() and torch.isfinite(big.targets).all()
+    for c in (0, 1):
+        r = float(torch.sqrt(torch.mean((big.planes[0, c] * big.scales[0, c]).double() ** 2)))
+        assert abs(r - 1.0) < 1e-4
+    # batch 2 of 128x128 images is 1 of 256x512 (at least one image per batch)
+    net, hist = PC.train([tiny, big], epochs=2, batch=2, lr=1e-3, val_frac=0.0, warmup=2,
+                         log=lambda m: print(m, flush=True))
+    assert hist["steps"] == 2 * (8 // 2 + 2 // 1)
+    assert all(math.isfinite(e["train_loss"]) for e in hist["epochs"])
+    # the trained network applies to either size
+    for ds in (tiny, big):
+        assert math.isfinite(PC.mean_loss(net, ds, torch.arange(2, device=ds.planes.device), 1))
