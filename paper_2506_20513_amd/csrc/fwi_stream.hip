@@ -31,6 +31,14 @@
 
 #include <type_traits>
 
+// Every fused multiply-add below is written out (fmaf), and the compiler may
+// not fuse anything else: each cell then sees the same sequence of IEEE
+// operations whichever code path (edge or interior strip, quiet or boundary
+// row, single or batched problem) computes it, so results do not depend on
+// the tiling.  The CPML terms are evaluated only where a CPML coefficient is
+// nonzero; elsewhere they would add an exact zero.
+#pragma clang fp contract(off)
+
 namespace fwi {
 namespace {
 
@@ -56,6 +64,16 @@ __device__ __forceinline__ T ldc(const T *base, unsigned idx) {
 }
 // The per-call cold arguments, read with scalar loads.
 using ColdRef = const FWI_AS_CONST StreamCold *;
+
+// The per-level slot pointers of a pass are walked from one base that is
+// made opaque at every row iteration: hoisted out of the row loop, eight
+// 64-bit pointers per kernel would not fit the scalar registers and would be
+// reloaded from spill slots at every use.
+template <class T>
+__device__ __forceinline__ T *row_base(T *p) {
+    asm volatile("" : "+s"(p));
+    return p;
+}
 
 // lane i receives lane i-1's value (lane 0 receives 0)
 __device__ __forceinline__ float from_left(float v) {
@@ -183,8 +201,11 @@ __device__ __forceinline__ WaveTile wave_tile(const Tiling &tl, int S, int NX, i
 // With zeros outside the grid, Ez = 0 and Ca = Cs = 0 on the PEC ring, the
 // H rows/columns that the E update never reads (Hx at j = NY-1, Hy at
 // i = NX-1) see a zero difference and stay zero, and ring Ez stays zero.
-// psi is a float4 (psi_hx, psi_hy, psi_ex, psi_ey).
-template <int K, bool EDGE, bool TAIL>
+// psi is a float4 (psi_hx, psi_hy, psi_ex, psi_ey).  LEV: 1 if the pass
+// writes every level's Ez (a.E_lev set), 0 if only the final state, 2 if
+// decided at run time; a fixed choice keeps the other stores' addresses out
+// of the scalar registers.
+template <int K, bool EDGE, bool TAIL, int LEV>
 __device__ __forceinline__ void fwd_body(const FwdStreamArgs &a, const WaveTile &w,
                                          float4 (*ring)[64]) {
     constexpr int OW = 64 - 2 * K;
@@ -214,6 +235,9 @@ __device__ __forceinline__ void fwd_body(const FwdStreamArgs &a, const WaveTile 
     const float *Cap = a.Ca;
     const float *Csp = a.Cs;
     const int rlast = min(NY - 1, y1 + nlev - 1);
+    const bool lev = LEV == 2 ? a.E_lev != nullptr : LEV == 1;
+    float *const elev0 = lev ? a.E_lev + so : nullptr;   // level 0 slot of the shot
+    const size_t lstr = a.lev_stride;
 
 #pragma unroll
     for (int l = 0; l < K; ++l) ring[l][lane] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -253,12 +277,18 @@ __device__ __forceinline__ void fwd_body(const FwdStreamArgs &a, const WaveTile 
     };
     load(y0 - K);
 
-    auto iter = [&](auto pc, int t) {
+    // QUIET: every row of the iteration is owned by the band and lies
+    // outside the y-direction CPML, the receiver rows and the source row, so
+    // the row-dependent branches are known to be off (same arithmetic).
+    auto iter = [&](auto pc, auto quiet, int t) {
         constexpr int p = decltype(pc)::value, q = 1 - p;
+        constexpr bool QUIET = decltype(quiet)::value;
         const int r = y0 - K + t;
         E_[q][0] = nE; Hx_[q][0] = nHx; Hy_[q][0] = nHy; Ca_[q][0] = nCa; Cs_[q][0] = nCs;
         ps0[q] = nPs;
         load(r + 1);
+        float *el = nullptr;
+        if (lev) el = row_base(elev0);
 #pragma unroll
         for (int l = 0; l < K; ++l) {
             if (TAIL && l >= nlev) continue;
@@ -266,8 +296,8 @@ __device__ __forceinline__ void fwd_body(const FwdStreamArgs &a, const WaveTile 
             const int j = r - 1 - l;
             const float pE = E_[p][l], pCa = Ca_[p][l], pCs = Cs_[p][l];
             const float hprev = (l + 1 < K) ? Hx_[p][l + 1] : hlast;
-            const bool jown = j >= y0 && j < y1;
-            if (a.record && jown && j >= rlo && j <= rhi) {    // stage 1
+            const bool jown = QUIET || (j >= y0 && j < y1);
+            if (!QUIET && a.record && jown && j >= rlo && j <= rhi) {    // stage 1
                 const int *rcol = cold->g.rcol, *ridx = cold->g.ridx;
                 int lo, hi;
                 rec_range(cold->g.rrow, rcol, s, NY, a.R, j, w.x0, w.x0 + OW, lo, hi);
@@ -276,39 +306,39 @@ __device__ __forceinline__ void fwd_body(const FwdStreamArgs &a, const WaveTile 
                     if (own && ldc(rcol, s * a.R + q2) == i)
                         stg(tr, (unsigned)ldc(ridx, s * a.R + q2), pE);
             }
-            const int ry = yrow(j, NY, npml);
+            const int ry = QUIET ? -1 : yrow(j, NY, npml);
             const bool yp = ry >= 0;
             const RowPml rp = yp ? row_pml(cold, j, ch, rdy) : r0;
             // stages 2-3: H to n+l+1/2
             const float dEy = E_[q][l] - pE;
             const float dEx = from_right(pE) - pE;
-            float hx = Hx_[p][l] - rp.chy * dEy;
-            float hy = Hy_[p][l] + c.chx * dEx;
+            float hx = fmaf(-rp.chy, dEy, Hx_[p][l]);
+            float hy = fmaf(c.chx, dEx, Hy_[p][l]);
             float4 ps = make_float4(0.f, 0.f, 0.f, 0.f);
             if (yp || xp) ps = l == 0 ? ps0[p] : ring[j & (K - 1)][lane];
             if (yp) {
-                ps.x = rp.bHy * ps.x + rp.aHy * dEy;
-                hx -= ch * ps.x;
+                ps.x = fmaf(rp.bHy, ps.x, rp.aHy * dEy);
+                hx = fmaf(-ch, ps.x, hx);
             }
             if (xp) {
-                ps.y = c.bHx * ps.y + c.aHx * dEx;
-                hy += ch * ps.y;
+                ps.y = fmaf(c.bHx, ps.y, c.aHx * dEx);
+                hy = fmaf(ch, ps.y, hy);
             }
             // stages 4-6: E to n+l+1
             const float dHy = hy - from_left(hy);
             const float dHx = hx - hprev;
-            float curl = dHy * c.cxE - dHx * rp.cyE;
+            float curl = fmaf(dHy, c.cxE, -(dHx * rp.cyE));
             if (xp) {
-                ps.z = c.bEx * ps.z + c.aEx * dHy;
+                ps.z = fmaf(c.bEx, ps.z, c.aEx * dHy);
                 curl += ps.z;
             }
             if (yp) {
-                ps.w = rp.bEy * ps.w + rp.aEy * dHx;
+                ps.w = fmaf(rp.bEy, ps.w, rp.aEy * dHx);
                 curl -= ps.w;
             }
-            float e = pCa * pE + pCs * curl;
-            if (j == sj && i == si)
-                e -= pCs * ldc(cold->g.wavelet + (size_t)s * a.nt, a.n + l) * a.src_scale;
+            float e = fmaf(pCa, pE, pCs * curl);
+            if (!QUIET && j == sj && i == si)
+                e = fmaf(-(pCs * ldc(cold->g.wavelet + (size_t)s * a.nt, a.n + l)), a.src_scale, e);
             if (l + 1 < K) {
                 E_[q][l + 1] = e; Hx_[q][l + 1] = hx; Hy_[q][l + 1] = hy;
                 Ca_[q][l + 1] = pCa; Cs_[q][l + 1] = pCs;
@@ -318,9 +348,9 @@ __device__ __forceinline__ void fwd_body(const FwdStreamArgs &a, const WaveTile 
             }
             if (jown && own) {
                 const unsigned k = (unsigned)(j * P + i);
-                if (a.E_lev) stg(a.E_lev + (size_t)l * a.lev_stride + so, k, e);
+                if (lev) stg(el, k, e);
                 if (last) {
-                    if (!a.E_lev) stg(a.E_out + so, k, e);
+                    if (!lev) stg(a.E_out + so, k, e);
                     stg(a.Hx_out + so, k, hx);
                     stg(a.Hy_out + so, k, hy);
                     if (yp) {
@@ -335,25 +365,42 @@ __device__ __forceinline__ void fwd_body(const FwdStreamArgs &a, const WaveTile 
                     }
                 }
             }
+            if (lev) el += lstr;
         }
     };
     const int T = (y1 - y0) + K + nlev;
-    for (int t = 0; t < T; t += 2) {
-        iter(std::integral_constant<int, 0>(), t);
-        iter(std::integral_constant<int, 1>(), t + 1);
+    const int qlo = max(y0, npml), qhi = min(y1, NY - 1 - npml) - 1;   // quiet rows
+    // Iterations t and t + 1 touch rows [r - K, r], r = y0 - K + t.  Quiet and
+    // other runs of iterations go to separate loops, so the registers of the
+    // rare branches are spilled around the quiet loop rather than inside it.
+    auto quiet = [&](int t) {
+        const int r = y0 - K + t;
+        return !TAIL && r - K >= qlo && r <= qhi && (sj < r - K || sj > r) &&
+               (!a.record || rhi < r - K || rlo > r);
+    };
+    int t = 0;
+    while (t < T) {
+        for (; t < T && !quiet(t); t += 2) {
+            iter(std::integral_constant<int, 0>(), std::false_type(), t);
+            iter(std::integral_constant<int, 1>(), std::false_type(), t + 1);
+        }
+        for (; t < T && quiet(t); t += 2) {
+            iter(std::integral_constant<int, 0>(), std::true_type(), t);
+            iter(std::integral_constant<int, 1>(), std::true_type(), t + 1);
+        }
     }
 }
 
-template <int K, bool TAIL>
+template <int K, bool TAIL, int LEV>
 __global__ __launch_bounds__(64) void k_fwd(FwdStreamArgs a) {
     static_assert((K & (K - 1)) == 0, "K must be a power of two");
     __shared__ float4 ring[K][64];
     const WaveTile w =
         wave_tile<K>(a.tl, a.S, a.NX, a.npml, xcd_logical(blockIdx.x, gridDim.x));
     if (w.edge)
-        fwd_body<K, true, TAIL>(a, w, ring);
+        fwd_body<K, true, TAIL, LEV>(a, w, ring);
     else
-        fwd_body<K, false, TAIL>(a, w, ring);
+        fwd_body<K, false, TAIL, LEV>(a, w, ring);
 }
 
 // A struct read from the constant address space dword by dword (scalar
@@ -390,9 +437,9 @@ __global__ __launch_bounds__(64) void k_fwd_tab(const FwdStreamArgs *tab, const 
     const FwdStreamArgs a = load_const(tab, m);
     const WaveTile w = wave_tile<K>(a.tl, a.S, a.NX, a.npml, (int)(lb - ldc(boff, m)));
     if (w.edge)
-        fwd_body<K, true, TAIL>(a, w, ring);
+        fwd_body<K, true, TAIL, 2>(a, w, ring);
     else
-        fwd_body<K, false, TAIL>(a, w, ring);
+        fwd_body<K, false, TAIL, 2>(a, w, ring);
 }
 
 // ---------------------------------------------------------------------------
@@ -449,13 +496,13 @@ __device__ __forceinline__ void adj_body(const AdjStreamArgs &a, const WaveTile 
     const float *Csp = a.Cs;
     const int rlast = min(NY - 1, y1 + nlev - 1);
 
-    // forward Ez^{n_l}(j) of level l (n_l = n_top - 1 - l), 0 off the grid
-    auto loadE = [&](int l, int j) {
-        return (j >= 0 && j < NY && inx)
-                   ? ldg(a.E_lev + (size_t)(a.n_top - 1 - l - a.n_base) * a.lev_stride + so,
-                         (unsigned)(j * P + i))
-                   : 0.f;
+    // forward Ez^{n_l}(j) of level l (n_l = n_top - 1 - l) from its slot el,
+    // 0 off the grid; level l's slot is lstr floats below level l-1's
+    auto loadE = [&](const float *el, int j) {
+        return (j >= 0 && j < NY && inx) ? ldg(el, (unsigned)(j * P + i)) : 0.f;
     };
+    const float *const etop = a.E_lev + (size_t)(a.n_top - 1 - a.n_base) * a.lev_stride + so;
+    const size_t lstr = a.lev_stride;
 
     float L_[2][K], Ca_[2][K], Cs_[2][K], Hx_[2][K], Hy_[2][K];
     float ldey_prev[K], en_pf[K];
@@ -465,7 +512,7 @@ __device__ __forceinline__ void adj_body(const AdjStreamArgs &a, const WaveTile 
         L_[0][l] = L_[1][l] = Ca_[0][l] = Ca_[1][l] = Cs_[0][l] = Cs_[1][l] = 0.f;
         Hx_[0][l] = Hx_[1][l] = Hy_[0][l] = Hy_[1][l] = 0.f;
         ldey_prev[l] = 0.f;
-        en_pf[l] = (TAIL && l >= nlev) ? 0.f : loadE(l, y0 - K - 1 - l);
+        en_pf[l] = (TAIL && l >= nlev) ? 0.f : loadE(etop - (size_t)l * lstr, y0 - K - 1 - l);
     }
     float4 ph0[2] = {make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f)};
     float nL = 0.f, nCa = 0.f, nCs = 0.f, nHx = 0.f, nHy = 0.f;
@@ -495,12 +542,16 @@ __device__ __forceinline__ void adj_body(const AdjStreamArgs &a, const WaveTile 
     };
     load(y0 - K);
 
-    auto iter = [&](auto pc, int t) {
+    // QUIET: as in the forward pass (rows j and j + 1 of every level clear of
+    // the y-direction CPML, the receiver rows and the source row).
+    auto iter = [&](auto pc, auto quiet, int t) {
         constexpr int p = decltype(pc)::value, q = 1 - p;
+        constexpr bool QUIET = decltype(quiet)::value;
         const int r = y0 - K + t;
         L_[q][0] = nL; Ca_[q][0] = nCa; Cs_[q][0] = nCs; Hx_[q][0] = nHx; Hy_[q][0] = nHy;
         ph0[q] = nPh;
         load(r + 1);
+        const float *el = row_base(etop);
 #pragma unroll
         for (int l = 0; l < K; ++l) {
             if (TAIL && l >= nlev) continue;
@@ -508,12 +559,14 @@ __device__ __forceinline__ void adj_body(const AdjStreamArgs &a, const WaveTile 
             const int j = r - 1 - l;
             const int n = a.n_top - 1 - l;
             const float en = en_pf[l];
-            en_pf[l] = loadE(l, j + 1);
+            en_pf[l] = loadE(el, j + 1);
+            el -= lstr;
             const float pL = L_[p][l], pCa = Ca_[p][l], pCs = Cs_[p][l];
-            const bool jown = j >= y0 && j < y1;
-            if (jown && j == sj && cold->src_adjoint && own && i == si)
+            const bool jown = QUIET || (j >= y0 && j < y1);
+            if (!QUIET && jown && j == sj && cold->src_adjoint && own && i == si)
                 stg(cold->src_adjoint + (size_t)s * a.nt, (unsigned)n, -pCs * pL * a.src_scale);
-            const int ry = yrow(j, NY, npml), ry1 = yrow(j + 1, NY, npml);
+            const int ry = QUIET ? -1 : yrow(j, NY, npml);
+            const int ry1 = QUIET ? -1 : yrow(j + 1, NY, npml);
             const bool yp = ry >= 0, yp1 = ry1 >= 0;
             const RowPml rp = yp ? row_pml(cold, j, ch, rdy) : r0;
             const RowPml rp1 = yp1 ? row_pml(cold, j + 1, ch, rdy) : r0;
@@ -521,30 +574,43 @@ __device__ __forceinline__ void adj_body(const AdjStreamArgs &a, const WaveTile 
             if (yp || xp) ph = l == 0 ? ph0[p] : ring[j & (K - 1)][lane];
             // A1: transposed E step, row j and the LDy of row j+1
             const float g = pCs * pL;
-            const float tx = ph.x + g, ty = ph.y - g;
-            const float ldx = g * c.cxE + c.aEx * tx;
-            const float ldy = -g * rp.cyE + rp.aEy * ty;
-            if (xp) ph.x = c.bEx * tx;
-            if (yp) ph.y = rp.bEy * ty;
+            float ldx = g * c.cxE;
+            float ldy = -g * rp.cyE;
+            if (xp) {
+                const float tx = ph.x + g;
+                ldx = fmaf(c.aEx, tx, ldx);
+                ph.x = c.bEx * tx;
+            }
+            if (yp) {
+                const float ty = ph.y - g;
+                ldy = fmaf(rp.aEy, ty, ldy);
+                ph.y = rp.bEy * ty;
+            }
             const float gn = Cs_[q][l] * L_[q][l];
             float ldyn = -gn * rp1.cyE;
             if (yp1) {
                 const float pey1 = l == 0 ? ph0[q].y : ring[(j + 1) & (K - 1)][lane].y;
-                ldyn += rp1.aEy * (pey1 - gn);
+                ldyn = fmaf(rp1.aEy, pey1 - gn, ldyn);
             }
             const float lhy = Hy_[p][l] + (ldx - from_right(ldx));
             const float lhx = Hx_[p][l] + (ldy - ldyn);
             // A2: transposed H step
-            const float t1 = ph.w + ch * lhy;
-            const float ldex = lhy * c.chx + c.aHx * t1;
-            if (xp) ph.w = c.bHx * t1;
-            const float t2 = ph.z - ch * lhx;
-            const float ldey = -lhx * rp.chy + rp.aHy * t2;
-            if (yp) ph.z = rp.bHy * t2;
-            float le = pCa * pL + (from_left(ldex) - ldex) + (ldey_prev[l] - ldey);
+            float ldex = lhy * c.chx;
+            if (xp) {
+                const float t1 = fmaf(ch, lhy, ph.w);
+                ldex = fmaf(c.aHx, t1, ldex);
+                ph.w = c.bHx * t1;
+            }
+            float ldey = -lhx * rp.chy;
+            if (yp) {
+                const float t2 = fmaf(-ch, lhx, ph.z);
+                ldey = fmaf(rp.aHy, t2, ldey);
+                ph.z = rp.bHy * t2;
+            }
+            float le = fmaf(pCa, pL, from_left(ldex) - ldex) + (ldey_prev[l] - ldey);
             ldey_prev[l] = ldey;
             // A3: adjoint source of step n
-            if (j >= rlo && j <= rhi) {
+            if (!QUIET && j >= rlo && j <= rhi) {
                 const int *rcol = cold->g.rcol, *ridx = cold->g.ridx;
                 int lo, hi;
                 rec_range(cold->g.rrow, rcol, s, NY, a.R, j, w.x0 - K, w.x0 - K + 64, lo, hi);
@@ -554,8 +620,8 @@ __device__ __forceinline__ void adj_body(const AdjStreamArgs &a, const WaveTile 
             }
             // imaging
             float2 acc = l == 0 ? make_float2(0.f, 0.f) : img[j & (K - 1)][lane];
-            acc.x += en * (le - pL);
-            acc.y += en * (le + pL);
+            acc.x = fmaf(en, le - pL, acc.x);
+            acc.y = fmaf(en, le + pL, acc.y);
             if (l + 1 < K) {
                 L_[q][l + 1] = le; Ca_[q][l + 1] = pCa; Cs_[q][l + 1] = pCs;
                 Hx_[q][l + 1] = lhx; Hy_[q][l + 1] = lhy;
@@ -585,9 +651,25 @@ __device__ __forceinline__ void adj_body(const AdjStreamArgs &a, const WaveTile 
         }
     };
     const int T = (y1 - y0) + K + nlev;
-    for (int t = 0; t < T; t += 2) {
-        iter(std::integral_constant<int, 0>(), t);
-        iter(std::integral_constant<int, 1>(), t + 1);
+    const int qlo = max(y0, npml), qhi = min(y1, NY - 1 - npml) - 2;   // rows j, j + 1 quiet
+    // Iterations t and t + 1 touch rows [r - K, r], r = y0 - K + t.  Quiet and
+    // other runs of iterations go to separate loops, so the registers of the
+    // rare branches are spilled around the quiet loop rather than inside it.
+    auto quiet = [&](int t) {
+        const int r = y0 - K + t;
+        return !TAIL && r - K >= qlo && r <= qhi && (sj < r - K || sj > r) &&
+               (rhi < r - K || rlo > r);
+    };
+    int t = 0;
+    while (t < T) {
+        for (; t < T && !quiet(t); t += 2) {
+            iter(std::integral_constant<int, 0>(), std::false_type(), t);
+            iter(std::integral_constant<int, 1>(), std::false_type(), t + 1);
+        }
+        for (; t < T && quiet(t); t += 2) {
+            iter(std::integral_constant<int, 0>(), std::true_type(), t);
+            iter(std::integral_constant<int, 1>(), std::true_type(), t + 1);
+        }
     }
 }
 
@@ -649,10 +731,18 @@ hipError_t launch_adj_table(const AdjStreamArgs *tab, const unsigned *boff, int 
 // nlev < depth takes the partial-pass variant.
 template <int K>
 hipError_t launch_fwd_depth(const FwdStreamArgs &a, unsigned nb, hipStream_t st) {
-    if (a.nlev == K)
-        hipLaunchKernelGGL((k_fwd<K, false>), dim3(nb), dim3(64), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_fwd<K, true>), dim3(nb), dim3(64), 0, st, a);
+    const bool full = a.nlev == K;
+    if (a.E_lev) {
+        if (full)
+            hipLaunchKernelGGL((k_fwd<K, false, 1>), dim3(nb), dim3(64), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_fwd<K, true, 1>), dim3(nb), dim3(64), 0, st, a);
+    } else {
+        if (full)
+            hipLaunchKernelGGL((k_fwd<K, false, 0>), dim3(nb), dim3(64), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_fwd<K, true, 0>), dim3(nb), dim3(64), 0, st, a);
+    }
     return hipGetLastError();
 }
 
