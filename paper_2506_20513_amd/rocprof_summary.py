@@ -34,7 +34,8 @@ import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("csrc/fwi_stream.hip", "csrc/fwi_internal.h")
+# the kernels, and the host code that picks their launch decomposition
+KERNEL_SOURCES = ("csrc/fwi_stream.hip", "csrc/fwi_internal.h", "csrc/fwi_host.cpp")
 STENCIL = ("k_fwd", "k_adj")
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
