@@ -73,18 +73,10 @@ hipError_t ok(int rc) { return rc == FWI_OK ? hipSuccess : hipErrorUnknown; }
 
 // Row bands of height `rows` (0 = the single-problem heuristic).
 void set_bands(Layout &L, int rows) {
-    if (rows <= 0) {
+    if (rows <= 0)
         make_tiling(L.d, L);
-        return;
-    }
-    constexpr int OW = 64 - 2 * kBatchDepth;
-    const int max_bands = (int)(sizeof(L.bands) / sizeof(int)) - 1;
-    L.nstrip = (L.d.NX + OW - 1) / OW;
-    const int h = std::max(rows, (L.d.NY + max_bands - 1) / max_bands);
-    int nb = 0;
-    for (int y = 0; y < L.d.NY; y += h) L.bands[nb++] = y;
-    L.nband = nb;
-    L.bands[nb] = L.d.NY;
+    else
+        fixed_bands(L, rows, kBatchDepth);
 }
 
 // The operations of one problem's gradient, in its own order, with keys.

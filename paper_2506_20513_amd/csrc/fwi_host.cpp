@@ -103,13 +103,13 @@ int choose_k(const Dims &d, int depth) {
 // leaves SIMDs idle; pick the band count with the least estimated time.  The
 // waves of one round do not all finish together, so the idle part of the
 // last round counts half (fitted to band-count sweeps on 2088x1064 x 64
-// shots, best at 4 bands, and 552x296 x 24 shots, best at 17).
-void make_tiling(const Dims &d, Layout &L) {
-    const int K = L.depth, OW = 64 - 2 * K;
-    const int max_bands = (int)(sizeof(L.bands) / sizeof(int)) - 1;
-    const double slots = 1024.0 * 4.0;   // 256 CUs x 4 SIMDs x ~4 resident waves
-    L.nstrip = (d.NX + OW - 1) / OW;
-    const double per_band = (double)d.S * L.nstrip;
+// shots, best at 4 bands for the forward kernel and 2 for the adjoint, and
+// on 552x296 x 24 shots, best at 17 for both).  `waves` is the kernel's
+// resident waves per SIMD.
+int pick_bands(const Dims &d, int K, int nstrip, double waves, int *bands) {
+    const int max_bands = 63;
+    const double slots = 256.0 * 4.0 * waves;   // 256 CUs x 4 SIMDs
+    const double per_band = (double)d.S * nstrip;
     int best = 1;
     double best_t = 1e300;
     for (int nb = 1; nb <= max_bands && nb <= (d.NY + 2 * K - 1) / (2 * K); ++nb) {
@@ -124,9 +124,39 @@ void make_tiling(const Dims &d, Layout &L) {
     }
     const int h = (d.NY + best - 1) / best;
     int nb = 0;
-    for (int y = 0; y < d.NY; y += h) L.bands[nb++] = y;
-    L.nband = nb;
-    L.bands[nb] = d.NY;
+    for (int y = 0; y < d.NY; y += h) bands[nb++] = y;
+    bands[nb] = d.NY;
+    return nb;
+}
+
+// Resident waves per SIMD of the stencil kernels (512 VGPRs per SIMD lane):
+// the forward kernels need 75-123 VGPRs (4 waves at depth 8; at depth 4 the
+// estimate stays at 4, which the sweeps above favour), the depth-8 adjoint
+// 165 (3 waves).
+constexpr double kFwdWaves = 4.0;
+double adj_waves(int depth) { return depth == kDepthLarge ? 3.0 : 4.0; }
+
+void make_tiling(const Dims &d, Layout &L) {
+    static_assert(sizeof(L.bands) / sizeof(int) == 64 && sizeof(L.abands) / sizeof(int) == 64,
+                  "band tables hold 63 bands");
+    const int K = L.depth, OW = 64 - 2 * K;
+    L.nstrip = (d.NX + OW - 1) / OW;
+    L.nband = pick_bands(d, K, L.nstrip, kFwdWaves, L.bands);
+    L.naband = pick_bands(d, K, L.nstrip, adj_waves(K), L.abands);
+}
+
+void fixed_bands(Layout &L, int rows, int depth) {
+    const int OW = 64 - 2 * depth;
+    const int max_bands = (int)(sizeof(L.bands) / sizeof(int)) - 1;
+    L.nstrip = (L.d.NX + OW - 1) / OW;
+    const int h = std::max(rows, (L.d.NY + max_bands - 1) / max_bands);
+    int nb = 0;
+    for (int y = 0; y < L.d.NY; y += h) {
+        L.bands[nb] = L.abands[nb] = y;
+        ++nb;
+    }
+    L.nband = L.naband = nb;
+    L.bands[nb] = L.abands[nb] = L.d.NY;
 }
 
 // Workspace layout for a mode (FWI_SAVE_* or -1 = fwi_gradient).
@@ -155,6 +185,7 @@ int make_layout(const Dims &d, int mode, Layout &L, int k, int depth) {
     L.off_ridx = take(S * d.R * sizeof(int));
     L.off_rspan = take(S * 2 * sizeof(int));
     L.off_bands = take(sizeof(L.bands));
+    L.off_abands = take(sizeof(L.abands));
     L.off_cold = take(sizeof(StreamCold));
     L.state_bytes = align_up(field) * 2 + align_up(xs) * 2 + align_up(ys) * 2;
     L.off_fwd[0] = take(L.state_bytes);
@@ -236,6 +267,8 @@ int upload_geometry(const Ptrs &P, const fwi_geom *g, const StreamCold &cold,
                            hipMemcpyHostToDevice, st));
     FWI_TRY(hipMemcpyAsync(P.i(P.L->off_bands), P.L->bands, sizeof(P.L->bands),
                            hipMemcpyHostToDevice, st));
+    FWI_TRY(hipMemcpyAsync(P.i(P.L->off_abands), P.L->abands, sizeof(P.L->abands),
+                           hipMemcpyHostToDevice, st));
     FWI_TRY(hipMemcpyAsync(P.base + P.L->off_cold, &cold, sizeof(StreamCold),
                            hipMemcpyHostToDevice, st));
     // pageable host sources: make sure the copies consumed them before the
@@ -275,6 +308,13 @@ Tiling tiling(const Ptrs &P) {
     t.nstrip = L.nstrip;
     t.nband = L.nband;
     t.depth = L.depth;
+    return t;
+}
+
+Tiling tiling_adj(const Ptrs &P) {
+    Tiling t = tiling(P);
+    t.bands = P.i(P.L->off_abands);
+    t.nband = P.L->naband;
     return t;
 }
 
@@ -334,7 +374,7 @@ AdjStreamArgs adj_args(const Ptrs &P) {
     a.NX = d.NX; a.NY = d.NY; a.npml = d.npml; a.pitch = d.pitch;
     a.W = d.W; a.S = d.S; a.R = d.R; a.nt = d.nt;
     a.n_top = a.n_base = a.nlev = a.cur = 0;
-    a.tl = tiling(P);
+    a.tl = tiling_adj(P);
     a.plane = d.plane; a.xs = d.xs; a.ys = d.ys;
     a.lev_stride = (size_t)d.S * d.plane;
     a.ch = (float)(d.dt / kMu0);

@@ -20,6 +20,8 @@ int stream_depth(const Dims &d);
 int choose_k(const Dims &d, int depth);
 // Row bands of the streaming decomposition (stored in L).
 void make_tiling(const Dims &d, Layout &L);
+// Row bands of height `rows` for both kernels (batched plans).
+void fixed_bands(Layout &L, int rows, int depth);
 // Workspace layout for a save mode (-1: fwi_gradient); k > 0 forces the
 // checkpoint interval (a multiple of the streaming depth).
 int make_layout(const Dims &d, int mode, Layout &L, int k = 0, int depth = 0);
@@ -78,7 +80,8 @@ struct Ptrs {
 int upload_geometry(const Ptrs &P, const fwi_geom *g, const StreamCold &cold, hipStream_t st);
 int zero_state(const State &s, const Dims &d, bool with_e, hipStream_t st);
 int copy_state(const State &dst, const State &src, const Dims &d, hipStream_t st);
-Tiling tiling(const Ptrs &P);
+Tiling tiling(const Ptrs &P);       // forward kernel
+Tiling tiling_adj(const Ptrs &P);   // adjoint kernel
 StreamCold make_cold(const Ptrs &P, const fwi_geom *g, float *traces, const float *residual,
                      float *src_adjoint);
 FwdStreamArgs fwd_args(const Ptrs &P);

@@ -61,11 +61,13 @@ struct Layout {
     int depth;         // temporal depth of the streaming passes
     int ncp;           // number of checkpoints
     int nslots;        // Ez slots
-    // streaming decomposition (see Tiling)
-    int nstrip, nband;
+    // streaming decomposition (see Tiling): row bands of the forward kernel
+    // and, chosen for its own occupancy, of the adjoint kernel
+    int nstrip, nband, naband;
     int bands[64];
+    int abands[64];
     size_t off_Ca, off_Cs, off_prof;
-    size_t off_src, off_rrow, off_rcol, off_ridx, off_rspan, off_bands, off_cold;
+    size_t off_src, off_rrow, off_rcol, off_ridx, off_rspan, off_bands, off_abands, off_cold;
     size_t off_fwd[2];
     size_t off_slots;
     size_t off_ckpt, ckpt_stride;
