@@ -83,12 +83,13 @@ struct Layout {
 // Time levels advanced per pass of the streaming kernels (temporal depth).
 // Depth 8 reads and writes each field row once per 8 steps, but the
 // dependency cone leaves a 64-lane strip 48 output columns (16 recomputed)
-// and the kernels need 103-159 VGPRs; depth 4 keeps 56 columns and 72-93
-// VGPRs.  Measured: depth 8 gives 5-7% more cell-updates per second on a
-// 2088x1064 grid, and is 12-38% slower on grids of 0.02-0.25 M cells, where
-// the longer pipeline start of every band weighs more.  A problem uses depth
-// 8 from kDepthLargeCells cells per shot on.  Batched problems always use
-// depth 4 (one depth for all merged passes).
+// and the kernels need 110-165 VGPRs; depth 4 keeps 56 columns and 75-100
+// VGPRs.  Measured: depth 8 gives 45% more cell-updates per second on a
+// 2088x1064 grid with 64 shots (300 against 207 G/s), and was 12-38% slower
+// on grids of 0.02-0.25 M cells, where the longer pipeline start of every
+// band weighs more.  A problem uses depth 8 from kDepthLargeCells cells per
+// shot on.  Batched problems always use depth 4 (one depth for all merged
+// passes).
 constexpr int kDepthSmall = 4;
 constexpr int kDepthLarge = 8;
 constexpr long long kDepthLargeCells = 1LL << 20;

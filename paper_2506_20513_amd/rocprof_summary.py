@@ -40,11 +40,19 @@ STENCIL = ("k_fwd", "k_adj")
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments and with runs of white space collapsed,
+    so that a change of comments alone keeps the hash."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(HERE, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(HERE, rel), encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 
