@@ -12,7 +12,10 @@ Pins (what fixes this oracle independently of itself) live in
 ``tests/test_oracle_pins.py``: the analytic line-source Hankel solution,
 PEC-cavity energy conservation, exact lossy decay, reciprocity, the adjoint
 dot-product test, central finite differences of the misfit, and CPML
-absorption against a reflection-free reference.
+absorption against a reflection-free reference; on square and on
+anisotropic cells (dx != dy), with the mirror symmetry about the diagonal
+and a ring of perfect-conductor cells (sigma > 100 S/m) against the plain
+PEC box.
 """
 from __future__ import annotations
 
@@ -201,16 +204,23 @@ class Problem:
         return tr, hist
 
     def adjoint_run(self, lam: State, n_hi: int, n_lo: int, src, rec, residual,
-                    hist, S1, S2, sadj=None):
-        """Run the adjoint recursion n = n_hi-1 .. n_lo (Algorithm 2)."""
+                    hist, S1, S2, sadj=None, hist_base: int = 0):
+        """Run the adjoint recursion n = n_hi-1 .. n_lo (Algorithm 2).
+        hist[k] holds Ez^{hist_base + k}; it must cover steps n_lo .. n_hi.
+        residual [nt][nrec] and sadj [nt] are indexed by the absolute step."""
         L = lib()
+        assert hist_base <= n_lo and hist.shape[0] >= n_hi - hist_base + 1
         si, sj = (-1, -1) if src is None else (int(src[0]), int(src[1]))
         recs = np.ascontiguousarray(rec, dtype=np.int32).reshape(-1, 2)
         res = np.ascontiguousarray(residual, dtype=np.float64)
         tmpx = np.zeros((self.NY, self.NX))
         tmpy = np.zeros((self.NY, self.NX))
+        # the C recursion indexes the history by the absolute step n: hand it
+        # the address where Ez^0 would sit (only steps >= hist_base are read)
+        h = np.ascontiguousarray(hist, dtype=np.float64)
+        hptr = ctypes.cast(h.ctypes.data - hist_base * self.NX * self.NY * 8, _dp)
         L.orc_adjoint_run(self._buf, *[_p(a) for a in lam.arrays()], n_hi, n_lo,
-                          si, sj, recs.shape[0], _pi(recs), _p(res), _p(hist),
+                          si, sj, recs.shape[0], _pi(recs), _p(res), hptr,
                           _p(S1), _p(S2),
                           _p(sadj) if sadj is not None else _null(_dp),
                           _p(tmpx), _p(tmpy))
@@ -253,6 +263,58 @@ class Problem:
             g_sig += gs
             sadjs.append(sadj)
         return g_eps, g_sig, (np.stack(sadjs) if want_sadj else None)
+
+    def gradient_checkpointed(self, src_ij, rec_ij, wavelet, observed, nt, K=None,
+                              shots=None, progress=None):
+        """gradient() holding only the full state (Ez, H, CPML memories)
+        every K steps instead of the whole Ez history: the adjoint takes the
+        segments last first, re-runs each one forward from its checkpoint
+        with its Ez history kept, and runs Algorithm 2 over it.  The
+        recursions and the order of every sum are those of gradient(), so
+        the results are the same bit for bit.  Memory: ceil(nt/K) states
+        and K+1 Ez planes (K defaults to about sqrt(7 nt), which balances
+        the two).  progress(shot, seconds) is called after each shot."""
+        import time
+        src_ij = np.asarray(src_ij).reshape(-1, 2)
+        rec_ij = np.asarray(rec_ij).reshape(src_ij.shape[0], -1, 2)
+        wavelet = np.asarray(wavelet, dtype=np.float64).reshape(src_ij.shape[0], -1)
+        observed = np.asarray(observed, dtype=np.float64)
+        shots = list(range(src_ij.shape[0]) if shots is None else shots)
+        K = max(1, int(round((7.0 * nt) ** 0.5))) if K is None else int(K)
+        J = 0.0
+        g_eps = np.zeros((self.NY, self.NX))
+        g_sig = np.zeros((self.NY, self.NX))
+        traces = []
+        for k, s in enumerate(shots):
+            t0 = time.perf_counter()
+            st = self.new_state()
+            ckpts = []
+            tr = np.zeros((nt, rec_ij.shape[1]))
+            for n0 in range(0, nt, K):
+                n1 = min(nt, n0 + K)
+                ckpts.append(st.copy())
+                tr[n0:n1], _ = self.run(st, n0, n1 - n0, src_ij[s], wavelet[s], rec_ij[s])
+            del st
+            r = tr - observed[k]
+            J += 0.5 * float(np.sum(r * r))
+            lam = self.new_state()
+            S1 = np.zeros((self.NY, self.NX))
+            S2 = np.zeros((self.NY, self.NX))
+            for c in range(len(ckpts) - 1, -1, -1):
+                n0 = c * K
+                n1 = min(nt, n0 + K)
+                seg = ckpts.pop()
+                _, hist = self.run(seg, n0, n1 - n0, src_ij[s], wavelet[s], None, True)
+                self.adjoint_run(lam, n1, n0, src_ij[s], rec_ij[s], r, hist, S1, S2,
+                                 hist_base=n0)
+                del hist, seg
+            ge, gs = self.finalize(S1, S2)
+            g_eps += ge
+            g_sig += gs
+            traces.append(tr)
+            if progress is not None:
+                progress(s, time.perf_counter() - t0)
+        return J, g_eps, g_sig, np.stack(traces)
 
     def finalize(self, S1, S2):
         g_eps = np.zeros((self.NY, self.NX))

@@ -26,6 +26,20 @@ identity of the exact discrete adjoint, or brute force on a tiny grid:
                          (13) in discrete form).
 * ``cpml_reflection``  - traces with the CPML against a run on a domain so
                          large that no wall reflection arrives in the window.
+* ``transpose_symmetry`` - on a grid with dx != dy, the problem mirrored
+                         about the diagonal (x and y, dx and dy, model,
+                         source and receivers exchanged) gives the same
+                         traces and the mirrored gradients.  Fixes which
+                         spacing and which CPML profile each axis uses.
+* ``pec_material_box`` - cells with sigma > 100 S/m are perfect conductors
+                         (Sec. 3.2, coefficient kernel): a ring of them
+                         inside a larger CPML grid must reproduce, bit for
+                         bit, the plain PEC box of the enclosed size, with
+                         zero field and zero gradient on and outside the ring.
+
+Energy, line-source, dot-product and finite-difference pins also run on
+anisotropic cells (dy about 0.73 dx), since Eqs. (3)-(5) and the stability
+bound Eq. (11) carry the two spacings separately.
 
 Each function returns a (value, bound) pair; a pin holds when value <= bound.
 """
@@ -48,47 +62,74 @@ def _dt(dx, dy=None):
 
 
 # ---------------------------------------------------------------------------
-def hankel_trace_error(dx, f0=1.0e9, rho=0.3, half=0.87, window=4.5e-9, eps_r=1.0):
-    """Relative L2 error of an oracle trace against the analytic field of a
-    line current I(t) in a homogeneous lossless medium:
+def _line_source_field(rho, nt, dt, f0, eps_r=1.0):
+    """Analytic Ez at distance rho from a line current I(t) (a Ricker
+    sampled like the oracle's wavelet) in a homogeneous lossless medium:
         Ez(rho, w) = -(w mu0 / 4) I(w) H0^(2)(k rho),  k = w sqrt(eps_r)/c0
-    (time dependence exp(+i w t)).  The PEC box is large enough that no wall
-    reflection reaches the receiver inside the window."""
+    (time dependence exp(+i w t)), sampled at t = n dt."""
     from scipy.special import hankel2
-    dt = _dt(dx)
-    nh = int(round(half / dx))
-    N = 2 * nh + 1
-    nt = int(math.ceil(window / dt))
-    P = oracle.Problem(np.full((N, N), eps_r), np.zeros((N, N)), 0, dx, dx, dt)
-    k = int(round(rho / dx))
-    w = ricker(nt, dt, f0, dtype=np.float64)
-    tr, _ = P.run(P.new_state(), 0, nt, (nh, nh), w, np.array([[nh + k, nh]], np.int32))
     M = 1 << 16
     I = ricker(M, dt, f0, dtype=np.float64)          # samples at (m + 1/2) dt
     om = 2.0 * np.pi * np.fft.rfftfreq(M, dt)
     Iw = np.fft.rfft(I) * np.exp(-1j * om * 0.5 * dt)  # re-reference to m dt
     G = np.zeros(om.shape, dtype=complex)
-    G[1:] = -(om[1:] * MU0 / 4.0) * hankel2(0, om[1:] * math.sqrt(eps_r) / C0 * (k * dx))
-    ana = np.fft.irfft(Iw * G, n=M)[:nt]
-    return float(np.linalg.norm(tr[:, 0] - ana) / np.linalg.norm(ana))
+    G[1:] = -(om[1:] * MU0 / 4.0) * hankel2(0, om[1:] * math.sqrt(eps_r) / C0 * rho)
+    return np.fft.irfft(Iw * G, n=M)[:nt]
+
+
+def hankel_trace_errors(dx, dy=None, f0=1.0e9, rho=0.3, half=0.87, window=4.5e-9,
+                        eps_r=1.0):
+    """Relative L2 errors of oracle traces against the analytic line-source
+    field, for one receiver about rho away along x and one along y.  The PEC
+    box is large enough that no wall reflection reaches a receiver inside
+    the window."""
+    dy = dx if dy is None else dy
+    dt = _dt(dx, dy)
+    nhx, nhy = int(round(half / dx)), int(round(half / dy))
+    NX, NY = 2 * nhx + 1, 2 * nhy + 1
+    nt = int(math.ceil(window / dt))
+    P = oracle.Problem(np.full((NY, NX), eps_r), np.zeros((NY, NX)), 0, dx, dy, dt)
+    kx, ky = int(round(rho / dx)), int(round(rho / dy))
+    w = ricker(nt, dt, f0, dtype=np.float64)
+    rec = np.array([[nhx + kx, nhy], [nhx, nhy + ky]], np.int32)
+    tr, _ = P.run(P.new_state(), 0, nt, (nhx, nhy), w, rec)
+    errs = []
+    for r, dist in enumerate((kx * dx, ky * dy)):
+        ana = _line_source_field(dist, nt, dt, f0, eps_r)
+        errs.append(float(np.linalg.norm(tr[:, r] - ana) / np.linalg.norm(ana)))
+    return errs
+
+
+def hankel_trace_error(dx, **kw):
+    """Error of the receiver along x on square cells."""
+    return hankel_trace_errors(dx, **kw)[0]
 
 
 def hankel_error():
-    """(coarse error, bound) and the observed convergence ratio."""
+    """Errors at dx = 6 mm and 3 mm (square cells, receiver along x)."""
     e1 = hankel_trace_error(0.006)
     e2 = hankel_trace_error(0.003)
     return e1, e2
 
 
+def hankel_error_aniso():
+    """Per-receiver errors (along x, along y) with dy = 0.733 dx, at
+    (6 mm, 4.4 mm) and at half those spacings."""
+    return hankel_trace_errors(0.006, 0.0044), hankel_trace_errors(0.003, 0.0022)
+
+
 # ---------------------------------------------------------------------------
-def pec_energy_drift(nsteps=10000):
+def pec_energy_drift(nsteps=10000, dy_ratio=1.0):
     """max |W^n - W^m| / |W| after the source stops, with
-    W^n = sum eps (Ez^n)^2 + mu0 sum H^{n-1/2} H^{n+1/2} (cell area dx dy)."""
+    W^n = sum eps (Ez^n)^2 + mu0 sum H^{n-1/2} H^{n+1/2} (cell area dx dy).
+    dy = dy_ratio * dx; the identity holds for any cell aspect ratio, and
+    only when each difference divides by its own axis' spacing."""
     rng = np.random.default_rng(11)
     NX, NY, dx = 40, 30, 0.01
-    dt = _dt(dx)
+    dy = dy_ratio * dx
+    dt = _dt(dx, dy)
     eps = 1.0 + 8.0 * rng.random((NY, NX))
-    P = oracle.Problem(eps, np.zeros((NY, NX)), 0, dx, dx, dt)
+    P = oracle.Problem(eps, np.zeros((NY, NX)), 0, dx, dy, dt)
     st = P.new_state()
     w = ricker(200, dt, 1.0e9, dtype=np.float64)
     w[120:] = 0.0
@@ -98,7 +139,7 @@ def pec_energy_drift(nsteps=10000):
         E_n, Hx_m, Hy_m = st.E.copy(), st.Hx.copy(), st.Hy.copy()
         P.run(st, 0, 1)
         W[n] = (np.sum(EPS0 * eps * E_n ** 2)
-                + MU0 * np.sum(Hx_m * st.Hx + Hy_m * st.Hy)) * dx * dx
+                + MU0 * np.sum(Hx_m * st.Hx + Hy_m * st.Hy)) * dx * dy
     return float((W.max() - W.min()) / abs(W.mean())), 1e-12
 
 
@@ -144,13 +185,15 @@ def reciprocity(npml):
 
 
 # ---------------------------------------------------------------------------
-def dot_product():
+def dot_product(dy_ratio=1.0):
     """<A w, r> against <w, A^T r> with random w and r, CPML on, lossy
-    heterogeneous medium, three receivers (two sharing a row)."""
+    heterogeneous medium, three receivers (two sharing a row); dy =
+    dy_ratio * dx."""
     NX, NY, dx, nt = 50, 40, 0.01, 400
-    dt = _dt(dx)
+    dy = dy_ratio * dx
+    dt = _dt(dx, dy)
     eps, sig = _hetero(4, NY, NX)
-    P = oracle.Problem(eps, sig, 6, dx, dx, dt, cpml_alpha_max=math.pi * 1e9 * EPS0)
+    P = oracle.Problem(eps, sig, 6, dx, dy, dt, cpml_alpha_max=math.pi * 1e9 * EPS0)
     rng = np.random.default_rng(5)
     src = np.array([[20, 9]], np.int32)
     rec = np.array([[[10, 11], [25, 30], [40, 11]]], np.int32)
@@ -163,11 +206,12 @@ def dot_product():
 
 
 # ---------------------------------------------------------------------------
-def fd_setup():
+def fd_setup(dy_ratio=1.0):
     nx = ny = 16
     npml, nt, dx, f0 = 4, 150, 0.02, 400e6
+    dy = dy_ratio * dx
     NX = NY = nx + 2 * npml
-    dt = _dt(dx)
+    dt = _dt(dx, dy)
     rng = np.random.default_rng(6)
     eps_t = 4.0 + 6.0 * rng.random((NY, NX))
     sig_t = 0.02 * rng.random((NY, NX))
@@ -178,30 +222,33 @@ def fd_setup():
     src = np.array([[12, 5]], np.int32)
     rec = np.array([[[8, 7], [16, 7], [12, 18]]], np.int32)
     kw = dict(cpml_alpha_max=math.pi * f0 * EPS0)
-    obs, _ = oracle.Problem(eps_t, sig_t, npml, dx, dx, dt, **kw).forward(src, rec, w, nt)
-    return dict(npml=npml, nt=nt, dx=dx, dt=dt, eps0=eps0, sig0=sig0, w=w,
+    obs, _ = oracle.Problem(eps_t, sig_t, npml, dx, dy, dt, **kw).forward(src, rec, w, nt)
+    return dict(npml=npml, nt=nt, dx=dx, dy=dy, dt=dt, eps0=eps0, sig0=sig0, w=w,
                 src=src, rec=rec, kw=kw, obs=obs)
 
 
-def fd_gradient():
+def fd_gradient(dy_ratio=1.0):
     """Worst relative error of the adjoint gradient against central finite
-    differences (h = 1e-4 of the value) at cells in the interior, at the
-    source, at a receiver, in the CPML, next to the PEC ring and on a model
-    interface, for both parameters, plus one random direction."""
-    c = fd_setup()
+    differences at cells in the interior, at the source, at a receiver, in
+    the CPML, next to the PEC ring and on a model interface, for both
+    parameters, plus one random direction.  The step is 1e-4 of the value
+    for eps_r and 1e-3 for sigma: J is nearly linear in sigma, so the larger
+    step keeps the difference of two nearly equal misfits well above their
+    rounding where a sigma gradient is small."""
+    c = fd_setup(dy_ratio)
 
     def J(e, s):
-        P = oracle.Problem(e, s, c["npml"], c["dx"], c["dx"], c["dt"], **c["kw"])
+        P = oracle.Problem(e, s, c["npml"], c["dx"], c["dy"], c["dt"], **c["kw"])
         tr, _ = P.forward(c["src"], c["rec"], c["w"], c["nt"])
         return 0.5 * float(np.sum((tr - c["obs"]) ** 2))
 
     e0, s0 = c["eps0"], c["sig0"]
-    P0 = oracle.Problem(e0, s0, c["npml"], c["dx"], c["dx"], c["dt"], **c["kw"])
+    P0 = oracle.Problem(e0, s0, c["npml"], c["dx"], c["dy"], c["dt"], **c["kw"])
     _, ge, gs, _ = P0.gradient(c["src"], c["rec"], c["w"], c["obs"], c["nt"])
     worst = 0.0
     for (j, i) in [(12, 12), (5, 12), (7, 16), (2, 2), (1, 12), (20, 3), (11, 9), (12, 9)]:
         for m, g, is_eps in ((e0, ge, True), (s0, gs, False)):
-            h = 1e-4 * m[j, i]
+            h = (1e-4 if is_eps else 1e-3) * m[j, i]
             mp, mm = m.copy(), m.copy()
             mp[j, i] += h
             mm[j, i] -= h
@@ -240,3 +287,100 @@ def cpml_reflection():
     off = pad - p
     trb, _ = Pb.forward(src + off, rec + off, w, cfg.nt)
     return float(np.linalg.norm(tr - trb) / np.linalg.norm(trb)), 1e-3
+
+
+# ---------------------------------------------------------------------------
+def transpose_symmetry():
+    """Largest relative difference between a lossy heterogeneous CPML
+    problem on cells dx x dy and the same problem mirrored about the
+    diagonal (model transposed, dx and dy exchanged, source and receiver
+    (i, j) swapped): traces must agree, and the gradients must be the
+    transposes of each other.  Mirroring maps Hx to -Hy and Hy to -Hx and
+    leaves Ez alone, so only a scheme that uses each axis' own spacing and
+    CPML profile is symmetric."""
+    NX, NY, dx, dy, nt, npml = 46, 38, 0.01, 0.0073, 300, 6
+    dt = _dt(dx, dy)
+    eps, sig = _hetero(21, NY, NX)
+    eps_t, sig_t = _hetero(22, NY, NX)
+    kw = dict(cpml_alpha_max=math.pi * 1e9 * EPS0, cpml_kappa_max=3.0)
+    src = np.array([[17, 9]], np.int32)
+    rec = np.array([[[9, 11], [30, 25], [36, 11]]], np.int32)
+    w = ricker(nt, dt, 1.0e9, dtype=np.float64)[None]
+    obs, _ = oracle.Problem(eps_t, sig_t, npml, dx, dy, dt, **kw).forward(src, rec, w, nt)
+    J, ge, gs, tr = oracle.Problem(eps, sig, npml, dx, dy, dt, **kw).gradient(
+        src, rec, w, obs, nt)
+    Pt = oracle.Problem(eps.T.copy(), sig.T.copy(), npml, dy, dx, dt, **kw)
+    Jt, get, gst, trt = Pt.gradient(src[:, ::-1].copy(), rec[:, :, ::-1].copy(), w, obs, nt)
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    return max(rel(trt, tr), rel(get.T, ge), rel(gst.T, gs), abs(Jt - J) / J), 1e-12
+
+
+# ---------------------------------------------------------------------------
+PEC_SIGMA_TEST = 1.0e3
+
+
+def pec_material_box():
+    """A ring of sigma = 1e3 S/m cells inside a larger CPML grid (on
+    anisotropic cells, lossy heterogeneous medium inside and outside the
+    ring) against the npml = 0 box whose outer PEC ring is that ring.
+    Returns the largest of: relative trace and interior-gradient
+    differences between the two, and the largest |Ez| and |gradient| on and
+    outside the ring relative to the interior's."""
+    dx, dy, nt = 0.01, 0.0073, 300
+    dt = _dt(dx, dy)
+    m, n = 30, 22                        # cells enclosed by the ring
+    bx, by = m + 2, n + 2                # box incl. its PEC ring
+    npml, oi, oj = 6, 11, 9              # ring's top-left corner in the big grid
+    NX, NY = bx + 2 * oi, by + 2 * oj
+    eps_b, sig_b = _hetero(31, by, bx)
+    eps_tb, sig_tb = _hetero(32, by, bx)
+    eps_out, sig_out = _hetero(33, NY, NX)
+
+    def embed(inner, outer):
+        big = outer.copy()
+        big[oj:oj + by, oi:oi + bx] = inner
+        ring = np.zeros((NY, NX), bool)
+        ring[oj:oj + by, oi:oi + bx] = True
+        ring[oj + 1:oj + by - 1, oi + 1:oi + bx - 1] = False
+        return big, ring
+    eps_big, ring = embed(eps_b, eps_out)
+    sig_big, _ = embed(sig_b, sig_out)
+    sig_big[ring] = PEC_SIGMA_TEST
+    eps_tbig, _ = embed(eps_tb, eps_out)
+    sig_tbig, _ = embed(sig_tb, sig_out)
+    sig_tbig[ring] = PEC_SIGMA_TEST
+    inside = np.zeros((NY, NX), bool)
+    inside[oj + 1:oj + by - 1, oi + 1:oi + bx - 1] = True
+
+    kw = dict(cpml_alpha_max=math.pi * 1e9 * EPS0)
+    w = ricker(nt, dt, 1.0e9, dtype=np.float64)[None]
+    src_b = np.array([[12, 8]], np.int32)
+    rec_b = np.array([[[3, 2], [20, 5], [29, 21]]], np.int32)
+    off = np.array([oi, oj], np.int32)
+    src, rec = src_b + off, rec_b + off
+    Pb = oracle.Problem(eps_b, sig_b, 0, dx, dy, dt, **kw)
+    Pbig = oracle.Problem(eps_big, sig_big, npml, dx, dy, dt, **kw)
+    obs_b, _ = oracle.Problem(eps_tb, sig_tb, 0, dx, dy, dt, **kw).forward(src_b, rec_b, w, nt)
+    obs, _ = oracle.Problem(eps_tbig, sig_tbig, npml, dx, dy, dt, **kw).forward(src, rec, w, nt)
+    Jb, geb, gsb, trb = Pb.gradient(src_b, rec_b, w, obs_b, nt)
+    J, ge, gs, tr = Pbig.gradient(src, rec, w, obs, nt)
+
+    # the field on and outside the ring, sampled every 25 steps
+    st = Pbig.new_state()
+    emax_out = emax_in = 0.0
+    for n0 in range(0, nt, 25):
+        Pbig.run(st, n0, 25, src[0], w[0])
+        emax_out = max(emax_out, float(np.abs(st.E[~inside]).max()))
+        emax_in = max(emax_in, float(np.abs(st.E[inside]).max()))
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    sl = (slice(oj, oj + by), slice(oi, oi + bx))
+    vals = [rel(tr, trb), rel(obs, obs_b), abs(J - Jb) / Jb,
+            rel(ge[sl], geb), rel(gs[sl], gsb),
+            emax_out / emax_in,
+            float(np.abs(ge[~inside]).max() / np.abs(ge[inside]).max()),
+            float(np.abs(gs[~inside]).max() / np.abs(gs[inside]).max())]
+    return max(vals), 1e-13
