@@ -51,13 +51,15 @@
  *   caller; "host" pointers are ordinary host memory read during the call.
  * - The library allocates nothing.  All scratch state lives in the
  *   caller-supplied device workspace `ws` of `ws_bytes` bytes (size from
- *   fwi_workspace_bytes; 256-byte alignment required).
+ *   fwi_workspace_bytes; 256-byte alignment required).  The one exception
+ *   is fwi_gradient_static, whose workspace is a static device array of the
+ *   library (see there).
  * - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
  *   stream).  Host arrays may be reused as soon as the call returns.
  *   Device outputs are valid once the stream reaches the end of the call.
- * - The library keeps no global mutable state.  Calls on different
- *   workspaces may run concurrently; calls sharing a workspace must be
- *   ordered on one stream.
+ * - Apart from that static array, the library keeps no global mutable
+ *   state.  Calls on different workspaces may run concurrently; calls
+ *   sharing a workspace must be ordered on one stream.
  *
  * Errors
  * ------
@@ -81,6 +83,8 @@ extern "C" {
 #define FWI_EGEOM (-3)       /* source/receiver outside the updated interior */
 #define FWI_ENOMEM (-4)      /* workspace missing, misaligned or too small   */
 #define FWI_EHIP (-5)        /* a HIP runtime call or kernel launch failed   */
+#define FWI_ESCRATCH (-7)    /* problem larger than fwi_gradient_static's
+                                static scratch (FWI_STATIC_SCRATCH_BYTES)   */
 
 /* How fdtd_forward keeps the forward field for a later fdtd_adjoint. */
 #define FWI_SAVE_NONE 0        /* traces only                               */
@@ -190,6 +194,27 @@ int fwi_gradient_timed(const fwi_grid *grid, const fwi_geom *geom,
                        const float *observed, double *misfit, float *grad_eps_r,
                        float *grad_sigma, float *traces_out, void *ws,
                        size_t ws_bytes, void *stream, fwi_timing *timing);
+
+/* ---- Allocation-free gradient -------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as fwi_gradient, with its workspace taken from a static device
+ * array of FWI_STATIC_SCRATCH_BYTES that the library holds on every device it
+ * runs on until the process ends.  The caller still passes inputs and
+ * outputs (device pointers as for fwi_gradient).  Problems whose
+ * fwi_workspace_bytes(..., -1, ...) exceeds the array get FWI_ESCRATCH; that
+ * check, like every argument check, runs on the host before any HIP call.
+ * The call allocates nothing.  The array is resolved for the current device
+ * on the first call made with it current; `stream` must belong to that
+ * device.  All calls on one device share its array: calls that overlap in
+ * time on one device race and must be ordered by the caller (one stream, or
+ * events).  Results equal fwi_gradient's bit for bit.  Like fwi_gradient,
+ * the call synchronises `stream` once while it uploads the geometry. */
+#define FWI_STATIC_SCRATCH_BYTES (64u << 20)
+int fwi_gradient_static(const fwi_grid *grid, const fwi_geom *geom,
+                        const float *eps_r, const float *sigma,
+                        const float *observed, double *misfit, float *grad_eps_r,
+                        float *grad_sigma, float *traces_out, void *stream);
 
 /* Checkpoint interval K that FWI_SAVE_CHECKPOINT uses for this shape
  * (host out `k`). */

@@ -16,7 +16,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfwi.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["fwi_kernels.hip", "fwi_stream.hip", "fwi_host.cpp", "fwi_batch.cpp", "fwi_nn.hip", "fwi_tv.hip"]
+SOURCES = ["fwi_kernels.hip", "fwi_stream.hip", "fwi_host.cpp", "fwi_batch.cpp", "fwi_nn.hip",
+           "fwi_tv.hip", "fwi_static.hip"]
 
 # Packed-FP32 instructions are disabled for all device code; hipcc's host pass
 # warns that it does not know the feature, which is harmless.

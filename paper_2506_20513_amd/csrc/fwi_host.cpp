@@ -743,6 +743,9 @@ extern "C" const char *fwi_strerror(int status) {
         case FWI_EGEOM: return "source or receiver outside the updated interior";
         case FWI_ENOMEM: return "workspace missing, misaligned or too small";
         case FWI_EHIP: return "HIP runtime or kernel launch failure";
+        case FWI_ESCRATCH:
+            return "problem needs more scratch than the static array of "
+                   "fwi_gradient_static holds (FWI_STATIC_SCRATCH_BYTES)";
         default: return "unknown status";
     }
 }

@@ -23,6 +23,8 @@ FWI_ECFL = -2
 FWI_EGEOM = -3
 FWI_ENOMEM = -4
 FWI_EHIP = -5
+FWI_ESCRATCH = -7
+STATIC_SCRATCH_BYTES = 64 << 20   # FWI_STATIC_SCRATCH_BYTES
 
 FWI_SAVE_NONE = 0
 FWI_SAVE_CHECKPOINT = 1
@@ -32,7 +34,7 @@ GRADIENT_WORKSPACE = -1   # fwi_workspace_bytes mode for fwi_gradient
 EXPORTED = ("fwi_workspace_bytes", "fdtd_forward", "fdtd_adjoint", "fwi_gradient",
             "fwi_gradient_timed", "fwi_checkpoint_interval", "fwi_strerror",
             "fwi_batch_workspace_bytes", "fwi_batch_plan_create", "fwi_batch_plan_run",
-            "fwi_batch_plan_info", "fwi_batch_plan_destroy")
+            "fwi_batch_plan_info", "fwi_batch_plan_destroy", "fwi_gradient_static")
 
 
 class FwiError(RuntimeError):
@@ -119,6 +121,7 @@ def lib() -> ctypes.CDLL:
         L.fwi_gradient.argtypes = [G, Q, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
         L.fwi_gradient_timed.argtypes = [G, Q, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp,
                                          ctypes.POINTER(fwi_timing)]
+        L.fwi_gradient_static.argtypes = [G, Q, vp, vp, vp, vp, vp, vp, vp, vp]
         L.fwi_strerror.argtypes = [ctypes.c_int]
         L.fwi_strerror.restype = ctypes.c_char_p
         BP = ctypes.POINTER(fwi_batch_problem)
@@ -130,7 +133,7 @@ def lib() -> ctypes.CDLL:
         L.fwi_batch_plan_destroy.argtypes = [vp]
         L.fwi_batch_plan_destroy.restype = None
         for name in ("fwi_workspace_bytes", "fwi_checkpoint_interval", "fdtd_forward",
-                     "fdtd_adjoint", "fwi_gradient", "fwi_gradient_timed",
+                     "fdtd_adjoint", "fwi_gradient", "fwi_gradient_timed", "fwi_gradient_static",
                      "fwi_batch_workspace_bytes", "fwi_batch_plan_create", "fwi_batch_plan_run",
                      "fwi_batch_plan_info"):
             getattr(L, name).restype = ctypes.c_int
@@ -273,6 +276,19 @@ def fwi_gradient_timed(grid, geom, eps_r, sigma, observed, misfit, grad_eps_r, g
                                   ctypes.byref(timing) if timing is not None else None)
     if raise_on_error:
         _check(st, "fwi_gradient_timed")
+    return st
+
+
+def fwi_gradient_static(grid, geom, eps_r, sigma, observed, misfit, grad_eps_r, grad_sigma,
+                        traces_out, stream=None, raise_on_error=True) -> int:
+    """fwi_gradient with the library's static device scratch as workspace
+    (no allocation; problems up to STATIC_SCRATCH_BYTES of workspace)."""
+    st = lib().fwi_gradient_static(ctypes.byref(grid), ctypes.byref(geom.c), _ptr(eps_r),
+                                   _ptr(sigma), _ptr(observed), _ptr(misfit),
+                                   _ptr(grad_eps_r), _ptr(grad_sigma), _ptr(traces_out),
+                                   _stream(stream))
+    if raise_on_error:
+        _check(st, "fwi_gradient_static")
     return st
 
 

@@ -39,7 +39,7 @@ def test_library_exports_every_declared_function(header):
 
 
 def test_strerror_covers_codes():
-    for code in (0, -1, -2, -3, -4, -5):
+    for code in (0, -1, -2, -3, -4, -5, -7):
         assert fwi.strerror(code) != "unknown status"
     assert fwi.strerror(-99) == "unknown status"
 
@@ -322,3 +322,27 @@ def test_checkpoint_interval_follows_the_temporal_depth():
         g = fwi.Geometry(src, rec, FAKE)
         k = fwi.checkpoint_interval(fwi.grid_from_config(cfg), g)
         assert k % depth == 0 and k <= cfg.nt, (cfg.name, k)
+
+
+def test_static_gradient_host_checks():
+    """fwi_gradient_static checks the problem's workspace against its static
+    scratch and its pointers on the host, before any HIP call: the
+    benchmark-size problem gets FWI_ESCRATCH, a null output FWI_EINVAL, a
+    bad grid the same status as fwi_gradient."""
+    cfg = I.config_large()
+    src, rec = I.geometry(cfg)
+    big = fwi.Geometry(src, rec, FAKE)
+    grid = fwi.grid_from_config(cfg)
+    assert fwi.workspace_bytes(grid, big, fwi.GRADIENT_WORKSPACE) > fwi.STATIC_SCRATCH_BYTES
+    st = fwi.fwi_gradient_static(grid, big, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None,
+                                 stream=0, raise_on_error=False)
+    assert st == fwi.FWI_ESCRATCH
+    _, tgrid, tgeom = _tiny()
+    assert fwi.workspace_bytes(tgrid, tgeom, fwi.GRADIENT_WORKSPACE) <= fwi.STATIC_SCRATCH_BYTES
+    st = fwi.fwi_gradient_static(tgrid, tgeom, FAKE, FAKE, FAKE, None, FAKE, FAKE, None,
+                                 stream=0, raise_on_error=False)
+    assert st == fwi.FWI_EINVAL
+    bad = fwi.grid_from_config(I.config_tiny().with_(nt=0))
+    st = fwi.fwi_gradient_static(bad, tgeom, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None,
+                                 stream=0, raise_on_error=False)
+    assert st == fwi.FWI_EINVAL
