@@ -54,9 +54,11 @@
  *   fwi_workspace_bytes; 256-byte alignment required).  The one exception
  *   is fwi_gradient_static, whose workspace is a static device array of the
  *   library (see there).
- * - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
- *   stream).  Host arrays may be reused as soon as the call returns.
- *   Device outputs are valid once the stream reaches the end of the call.
+ * - Every call runs on `stream` (a hipStream_t; NULL = the null stream).
+ *   Host arrays may be reused as soon as the call returns.  The forward,
+ *   adjoint and gradient calls return once the stream has finished them
+ *   (see Errors); the batched runs are asynchronous, and their device
+ *   outputs are valid once the stream reaches the end of the run.
  * - Apart from that static array, the library keeps no global mutable
  *   state.  Calls on different workspaces may run concurrently; calls
  *   sharing a workspace must be ordered on one stream.
@@ -66,6 +68,16 @@
  * Every entry point returns FWI_OK or a negative status.  All argument
  * checks run on the host before any HIP call, so an invalid call launches
  * nothing and leaves every output untouched.
+ *
+ * fdtd_forward, fdtd_adjoint and fwi_gradient (and its timed and static
+ * variants) end with a finiteness check of what they wrote: FP64 sums of
+ * squares of the traces (forward) or of both gradients (adjoint, gradient),
+ * and the misfit (gradient).  They wait for `stream` to reach that check
+ * and return FWI_ENONFINITE if any of those values holds a NaN or an
+ * infinity, for instance from a NaN in the observed data or the model.  The
+ * outputs are written all the same.  These calls therefore return with the
+ * stream drained; the batched plans (below) run asynchronously and do not
+ * check.
  */
 #ifndef FWI_H
 #define FWI_H
@@ -83,6 +95,8 @@ extern "C" {
 #define FWI_EGEOM (-3)       /* source/receiver outside the updated interior */
 #define FWI_ENOMEM (-4)      /* workspace missing, misaligned or too small   */
 #define FWI_EHIP (-5)        /* a HIP runtime call or kernel launch failed   */
+#define FWI_ENONFINITE (-6)  /* the call ran to the end, but its outputs hold
+                                a NaN or an infinity (see Errors above)      */
 #define FWI_ESCRATCH (-7)    /* problem larger than fwi_gradient_static's
                                 static scratch (FWI_STATIC_SCRATCH_BYTES)   */
 
@@ -169,7 +183,10 @@ int fwi_gradient(const fwi_grid *grid, const fwi_geom *geom,
 /* Per-kernel timing for roofline accounting.  The paper reports only whole
  * epoch wall times (Sec. 4, Tables 2-5); this records HIP events on `stream`
  * around every `sample_every`-th launch of each hot kernel of one
- * fwi_gradient call and reports their mean durations. */
+ * fwi_gradient call and reports their mean durations.  Three kinds:
+ * "k_fwd_sweep" (forward passes that keep only the final state),
+ * "k_fwd_reforward" (the segment re-forward, which also writes Ez of every
+ * step) and "k_adj" (adjoint and imaging). */
 #define FWI_TIMING_MAX_KINDS 8
 typedef struct fwi_kernel_time {
     char name[32];             /* kernel name as it appears in profiler traces */

@@ -186,16 +186,25 @@ class Problem:
         return State(self.NX, self.NY)
 
     def run(self, st: State, n0: int, nsteps: int, src=None, wavelet=None,
-            rec=None, keep_history=False):
+            rec=None, keep_history=False, hist_buf=None):
         """Advance st by nsteps forward steps (Algorithm 1).  Returns
-        (traces [nsteps][nrec] or None, history [nsteps+1][NY][NX] or None)."""
+        (traces [nsteps][nrec] or None, history [nsteps+1][NY][NX] or None).
+        hist_buf: an existing float64 array of at least nsteps+1 planes to
+        write the history into (its leading planes are returned)."""
         L = lib()
         si, sj = (-1, -1) if src is None else (int(src[0]), int(src[1]))
         w = None if wavelet is None else np.ascontiguousarray(wavelet, dtype=np.float64)
         recs = None if rec is None else np.ascontiguousarray(rec, dtype=np.int32).reshape(-1, 2)
         nrec = 0 if recs is None else recs.shape[0]
         tr = np.zeros((nsteps, nrec)) if nrec else None
-        hist = np.zeros((nsteps + 1, self.NY, self.NX)) if keep_history else None
+        hist = None
+        if keep_history:
+            if hist_buf is not None:
+                assert hist_buf.dtype == np.float64 and hist_buf.flags.c_contiguous
+                assert hist_buf.shape[0] >= nsteps + 1 and hist_buf.shape[1:] == (self.NY, self.NX)
+                hist = hist_buf[:nsteps + 1]
+            else:
+                hist = np.zeros((nsteps + 1, self.NY, self.NX))
         L.orc_forward_run(self._buf, *[_p(a) for a in st.arrays()], n0, nsteps,
                           si, sj, _p(w) if w is not None else _null(_dp),
                           nrec, _pi(recs) if nrec else _null(_ip),
@@ -300,14 +309,16 @@ class Problem:
             lam = self.new_state()
             S1 = np.zeros((self.NY, self.NX))
             S2 = np.zeros((self.NY, self.NX))
+            buf = np.empty((min(K, nt) + 1, self.NY, self.NX))   # every plane is written
             for c in range(len(ckpts) - 1, -1, -1):
                 n0 = c * K
                 n1 = min(nt, n0 + K)
                 seg = ckpts.pop()
-                _, hist = self.run(seg, n0, n1 - n0, src_ij[s], wavelet[s], None, True)
+                _, hist = self.run(seg, n0, n1 - n0, src_ij[s], wavelet[s], None, True, buf)
                 self.adjoint_run(lam, n1, n0, src_ij[s], rec_ij[s], r, hist, S1, S2,
                                  hist_base=n0)
                 del hist, seg
+            del buf
             ge, gs = self.finalize(S1, S2)
             g_eps += ge
             g_sig += gs

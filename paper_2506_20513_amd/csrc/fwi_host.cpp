@@ -223,9 +223,24 @@ int make_layout(const Dims &d, int mode, Layout &L, int k, int depth) {
         L.off_trc = take(tr);
         L.off_mis = take(kMisfitBlocks * sizeof(double));
     }
+    L.off_chk = take(kMisfitBlocks * sizeof(double) + sizeof(int));
     L.total = off;
     make_tiling(d, L);
     return FWI_OK;
+}
+
+// End-of-call finiteness check of a call's outputs (FP64 sums of squares of
+// up to two float arrays and an optional device double): waits for the
+// stream and returns FWI_ENONFINITE if any of them holds a NaN or infinity.
+int check_finite(const Ptrs &P, const float *a, size_t na, const float *b, size_t nb,
+                 const double *scalar, hipStream_t st) {
+    double *partials = reinterpret_cast<double *>(P.base + P.L->off_chk);
+    int *flag = reinterpret_cast<int *>(partials + kMisfitBlocks);
+    FWI_TRY(launch_finite_check(a, na, b, nb, scalar, partials, flag, st));
+    int h = 0;
+    FWI_TRY(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    FWI_TRY(hipStreamSynchronize(st));
+    return h ? FWI_ENONFINITE : FWI_OK;
 }
 
 // Geometry to the device: sources, and per shot the receivers sorted by
@@ -398,15 +413,18 @@ namespace {
 
 using namespace host;
 
-// Optional per-kernel timing with HIP events on the call's stream.
-enum Kind { K_FWD = 0, K_ADJ = 1, K_NKINDS = 2 };
-const char *const kKindName[K_NKINDS] = {"k_fwd", "k_adj"};
+// Optional per-kernel timing with HIP events on the call's stream.  The
+// forward kernel is timed as two kinds: passes that write only the final
+// state (the forward sweep, k_fwd<K, *, 0>) and passes that write every
+// level's Ez (the segment re-forward, k_fwd<K, *, 1>).
+enum Kind { K_FWD_SWEEP = 0, K_FWD_REFWD = 1, K_ADJ = 2, K_NKINDS = 3 };
+const char *const kKindName[K_NKINDS] = {"k_fwd_sweep", "k_fwd_reforward", "k_adj"};
 
 struct Timer {
     fwi_timing *t = nullptr;
     hipStream_t st = nullptr;
-    int launches[K_NKINDS] = {0, 0};
-    double updates[K_NKINDS] = {0, 0};
+    int launches[K_NKINDS] = {0, 0, 0};
+    double updates[K_NKINDS] = {0, 0, 0};
     struct Rec { int kind; hipEvent_t a, b; };
     std::vector<Rec> recs;
     bool failed = false;
@@ -433,8 +451,8 @@ struct Timer {
 
     int finish() {
         if (!t) return FWI_OK;
-        double sum[K_NKINDS] = {0, 0};
-        int cnt[K_NKINDS] = {0, 0};
+        double sum[K_NKINDS] = {0, 0, 0};
+        int cnt[K_NKINDS] = {0, 0, 0};
         int rc = FWI_OK;
         if (hipStreamSynchronize(st) != hipSuccess) rc = FWI_EHIP;
         for (auto &r : recs) {
@@ -495,7 +513,8 @@ int forward_passes(const Ptrs &P, FwdStreamArgs a, int n0, int n1, int &cur, EIn
         a.Hy_in = fs[cur].Hy;
         a.Hx_out = fs[cur ^ 1].Hx;
         a.Hy_out = fs[cur ^ 1].Hy;
-        FWI_TRY(tm.run(K_FWD, all * a.nlev, [&] { return launch_fwd_stream(a, st); }));
+        FWI_TRY(tm.run(a.E_lev ? K_FWD_REFWD : K_FWD_SWEEP, all * a.nlev,
+                       [&] { return launch_fwd_stream(a, st); }));
         cur ^= 1;
     }
     return FWI_OK;
@@ -669,7 +688,11 @@ extern "C" int fdtd_forward(const fwi_grid *grid, const fwi_geom *geom,
     Timer tm;
     Ptrs P{static_cast<char *>(ws), &L};
     const StreamCold cold = make_cold(P, geom, traces, nullptr, nullptr);
-    return do_forward(L, geom, cold, eps_r, sigma, ws, static_cast<hipStream_t>(stream), tm);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    rc = do_forward(L, geom, cold, eps_r, sigma, ws, st, tm);
+    if (rc != FWI_OK) return rc;
+    const Dims &d = L.d;
+    return check_finite(P, traces, (size_t)d.S * d.nt * d.R, nullptr, 0, nullptr, st);
 }
 
 extern "C" int fdtd_adjoint(const fwi_grid *grid, const fwi_geom *geom,
@@ -689,7 +712,10 @@ extern "C" int fdtd_adjoint(const fwi_grid *grid, const fwi_geom *geom,
     rc = upload_geometry(P, geom, cold, st);
     if (rc != FWI_OK) return rc;
     Timer tm;
-    return do_adjoint(L, eps_r, sigma, grad_eps_r, grad_sigma, ws, st, tm);
+    rc = do_adjoint(L, eps_r, sigma, grad_eps_r, grad_sigma, ws, st, tm);
+    if (rc != FWI_OK) return rc;
+    const size_t cells = (size_t)L.d.NX * L.d.NY;
+    return check_finite(P, grad_eps_r, cells, grad_sigma, cells, nullptr, st);
 }
 
 extern "C" int fwi_gradient_timed(const fwi_grid *grid, const fwi_geom *geom,
@@ -723,7 +749,10 @@ extern "C" int fwi_gradient_timed(const fwi_grid *grid, const fwi_geom *geom,
         if (rc == FWI_OK) rc = do_adjoint(L, eps_r, sigma, grad_eps_r, grad_sigma, ws, st, tm);
     }
     const int rc2 = tm.finish();
-    return rc != FWI_OK ? rc : rc2;
+    if (rc != FWI_OK) return rc;
+    if (rc2 != FWI_OK) return rc2;
+    const size_t cells = (size_t)d.NX * d.NY;
+    return check_finite(P, grad_eps_r, cells, grad_sigma, cells, misfit, st);
 }
 
 extern "C" int fwi_gradient(const fwi_grid *grid, const fwi_geom *geom,
@@ -743,6 +772,8 @@ extern "C" const char *fwi_strerror(int status) {
         case FWI_EGEOM: return "source or receiver outside the updated interior";
         case FWI_ENOMEM: return "workspace missing, misaligned or too small";
         case FWI_EHIP: return "HIP runtime or kernel launch failure";
+        case FWI_ENONFINITE:
+            return "the call completed but its misfit, gradients or traces hold NaN or Inf";
         case FWI_ESCRATCH:
             return "problem needs more scratch than the static array of "
                    "fwi_gradient_static holds (FWI_STATIC_SCRATCH_BYTES)";

@@ -74,6 +74,7 @@ struct Layout {
     size_t off_adj[2];
     size_t off_S1, off_S2;    // per-shot [S][NY][pitch]
     size_t off_res, off_trc, off_mis;
+    size_t off_chk;       // finiteness check: kMisfitBlocks partials, then the flag
     size_t state_bytes;   // one forward State (without E)
     size_t total;
 };
@@ -176,6 +177,12 @@ hipError_t launch_gradient_finalize(const float *eps_r, const float *sigma,
 hipError_t launch_residual_misfit(const float *traces, const float *observed,
                                   float *residual, size_t n, double *partials,
                                   double *misfit, hipStream_t st);
+// Sets *flag (device int) to 1 if a[0..na) or b[0..nb) holds a NaN or an
+// infinity, or if *scalar (device, may be null) is not finite; else 0.
+// partials: kMisfitBlocks doubles of scratch.
+hipError_t launch_finite_check(const float *a, size_t na, const float *b, size_t nb,
+                               const double *scalar, double *partials, int *flag,
+                               hipStream_t st);
 // streaming kernels (fwi_stream.hip)
 hipError_t launch_fwd_stream(const FwdStreamArgs &a, hipStream_t st);
 hipError_t launch_adj_stream(const AdjStreamArgs &a, hipStream_t st);

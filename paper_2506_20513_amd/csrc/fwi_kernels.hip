@@ -159,7 +159,60 @@ __global__ __launch_bounds__(256) void k_misfit_final(const double *__restrict__
     if (threadIdx.x == 0) *misfit = 0.5 * red[0];
 }
 
+// FP64 sums of squares of two float arrays (the gradient-norm reduction),
+// per-block partials in a fixed order.  A sum is non-finite exactly when an
+// element is: the square of any finite float fits a double many times over.
+__global__ __launch_bounds__(256) void k_sumsq2(const float *__restrict__ a, size_t na,
+                                                const float *__restrict__ b, size_t nb,
+                                                double *__restrict__ partials) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (size_t t = t0; t < na; t += stride) acc += (double)a[t] * (double)a[t];
+    for (size_t t = t0; t < nb; t += stride) acc += (double)b[t] * (double)b[t];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+// flag = 1 if the summed partials, or the optional scalar, are not finite.
+__global__ __launch_bounds__(256) void k_finite_flag(const double *__restrict__ partials,
+                                                     int np, const double *__restrict__ scalar,
+                                                     int *__restrict__ flag) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < np; t += 256) acc += partials[t];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        bool bad = !isfinite(red[0]);
+        if (scalar) bad = bad || !isfinite(*scalar);
+        *flag = bad ? 1 : 0;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_finite_check(const float *a, size_t na, const float *b, size_t nb,
+                               const double *scalar, double *partials, int *flag,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_sumsq2, dim3(kMisfitBlocks), dim3(256), 0, st, a, na, b, nb,
+                       partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_finite_flag, dim3(1), dim3(256), 0, st, partials, kMisfitBlocks,
+                       scalar, flag);
+    return hipGetLastError();
+}
 
 hipError_t launch_coefficients(const float *eps_r, const float *sigma, float *Ca,
                                float *Cs, int NX, int NY, int pitch, double dt,

@@ -496,10 +496,13 @@ __device__ __forceinline__ void adj_body(const AdjStreamArgs &a, const WaveTile 
     const float *Csp = a.Cs;
     const int rlast = min(NY - 1, y1 + nlev - 1);
 
-    // forward Ez^{n_l}(j) of level l (n_l = n_top - 1 - l) from its slot el,
-    // 0 off the grid; level l's slot is lstr floats below level l-1's
+    // forward Ez^{n_l}(j) of level l (n_l = n_top - 1 - l) from its slot el;
+    // level l's slot is lstr floats below level l-1's.  Only the imaging sums
+    // use it, and only the cells the wave owns (its band's rows, its owned
+    // columns) store those, so other cells skip the load and take 0: their
+    // values are another wave's to image.
     auto loadE = [&](const float *el, int j) {
-        return (j >= 0 && j < NY && inx) ? ldg(el, (unsigned)(j * P + i)) : 0.f;
+        return (j >= y0 && j < y1 && own) ? ldg(el, (unsigned)(j * P + i)) : 0.f;
     };
     const float *const etop = a.E_lev + (size_t)(a.n_top - 1 - a.n_base) * a.lev_stride + so;
     const size_t lstr = a.lev_stride;

@@ -23,6 +23,7 @@ FWI_ECFL = -2
 FWI_EGEOM = -3
 FWI_ENOMEM = -4
 FWI_EHIP = -5
+FWI_ENONFINITE = -6
 FWI_ESCRATCH = -7
 STATIC_SCRATCH_BYTES = 64 << 20   # FWI_STATIC_SCRATCH_BYTES
 

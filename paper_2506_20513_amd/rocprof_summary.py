@@ -36,7 +36,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 # the kernels, and the host code that picks their launch decomposition
 KERNEL_SOURCES = ("csrc/fwi_stream.hip", "csrc/fwi_internal.h", "csrc/fwi_host.cpp")
-STENCIL = ("k_fwd", "k_adj")
+STENCIL = ("k_fwd_sweep", "k_fwd_reforward", "k_adj")
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
@@ -57,8 +57,17 @@ def kernel_source_hash() -> str:
 
 
 def short_name(name: str) -> str | None:
-    m = re.search(r"::(k_\w+)<", name)
-    return m.group(1) if m else None
+    """The benchmark's name for a kernel of a trace: the single-problem
+    forward kernel k_fwd<K, TAIL, LEV> is k_fwd_sweep for LEV = 0 (only the
+    final state written) and k_fwd_reforward for LEV = 1 (every level's Ez
+    written); other kernels keep their own name."""
+    m = re.search(r"::(k_\w+)<([^>]*)>", name)
+    if not m:
+        return None
+    if m.group(1) == "k_fwd":
+        lev = m.group(2).split(",")[-1].strip()
+        return {"0": "k_fwd_sweep", "1": "k_fwd_reforward"}.get(lev, "k_fwd")
+    return m.group(1)
 
 
 def _csv(run_dir: str, suffix: str):

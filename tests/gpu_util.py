@@ -78,3 +78,46 @@ class Run:
 
 def np_(t):
     return t.detach().cpu().numpy()
+
+
+def gradient_regions(shape, npml, src, rec, radius=3):
+    """Named boolean masks of the total grid for per-region gradient checks:
+    each CPML strip (left, right, top, bottom; the PEC ring excluded), the
+    deep half of the interior, and the interior with a `radius`-cell disc
+    around every source and receiver removed."""
+    NY, NX = shape
+    jj, ii = np.mgrid[0:NY, 0:NX]
+    upd = (ii >= 1) & (ii <= NX - 2) & (jj >= 1) & (jj <= NY - 2)
+    interior = (ii >= npml) & (ii <= NX - 1 - npml) & (jj >= npml) & (jj <= NY - 1 - npml)
+    out = {}
+    if npml > 0:
+        out["cpml_left"] = upd & (ii < npml)
+        out["cpml_right"] = upd & (ii > NX - 1 - npml)
+        out["cpml_top"] = upd & (jj < npml)
+        out["cpml_bottom"] = upd & (jj > NY - 1 - npml)
+    out["deep_half"] = interior & (jj >= npml + (NY - 2 * npml) // 2)
+    out["interior_masked"] = interior & mask_near(shape, src, rec, radius)
+    return out
+
+
+def region_errors(g, og, regions, floor=1e-3):
+    """Relative L2 error of g against og in every region.  A region that
+    holds less than `floor` of og's whole norm (one the waves barely reach in
+    the window) is measured against that floor instead of its own norm: FP32
+    rounding leaves errors of about 1e-7 to 1e-6 of the whole norm anywhere
+    the waves have been, which a nearly empty region cannot be held to
+    relative to itself."""
+    g = np.asarray(g, dtype=np.float64)
+    og = np.asarray(og, dtype=np.float64)
+    whole = np.linalg.norm(og)
+    out = {}
+    for k, m in regions.items():
+        ref = max(np.linalg.norm(og[m]), floor * whole)
+        out[k] = float(np.linalg.norm(g[m] - og[m]) / ref) if ref > 0 else 0.0
+    return out
+
+
+def late_window(tr, frac=1.0 / 3.0):
+    """The last `frac` of the time samples of traces [S][nt][R]."""
+    nt = tr.shape[1]
+    return tr[:, nt - max(1, int(round(nt * frac))):, :]

@@ -39,7 +39,7 @@ def test_library_exports_every_declared_function(header):
 
 
 def test_strerror_covers_codes():
-    for code in (0, -1, -2, -3, -4, -5, -7):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert fwi.strerror(code) != "unknown status"
     assert fwi.strerror(-99) == "unknown status"
 

@@ -2,6 +2,8 @@
 
 - traces() with a loss of 1/2 sum (traces - observed)^2 back-propagates to
   the same gradient the fused fwi_gradient call returns;
+- traces() under another loss back-propagates to the oracle's adjoint
+  gradient of that loss;
 - misfit() scales its stored gradient by the incoming gradient;
 - a backward pass after the problem ran another forward raises;
 - a short multiscale L-BFGS inversion on the 128x128 workload lowers the
@@ -60,6 +62,50 @@ def test_traces_backward_matches_fused_gradient(case):
         print("traces-backward vs fused gradient", err, flush=True)
         assert err <= 1e-6
     assert abs(float(loss) - float(mis)) <= 1e-5 * float(mis)
+
+
+def test_traces_backward_matches_oracle_adjoint():
+    """traces() under a loss that is not the misfit: L = sum q * traces +
+    1/2 sum (traces - observed)^2 with fixed random weights q.  Its backward
+    feeds dL/dtraces to the HIP adjoint; the oracle runs its own adjoint
+    (Algorithm 2) with the same adjoint source evaluated at its own traces.
+    Gradients within 1e-3, the loss within 1e-4 (relative)."""
+    import torch
+
+    import oracle
+    from paper_2506_20513_amd import autograd as AG
+    from tests.gpu_util import rel_l2
+    cfg = I.config_tiny().with_(nt=600)
+    e, s, e0, s0 = I.model_for(cfg)
+    src, rec = I.geometry(cfg)
+    wn = I.wavelets(cfg)
+    kw = dict(cpml_order=cfg.cpml_order, cpml_sigma_scale=cfg.cpml_sigma_scale,
+              cpml_kappa_max=cfg.cpml_kappa_max, cpml_alpha_max=cfg.cpml_alpha_max)
+    obs, _ = oracle.Problem(e, s, cfg.npml, cfg.dx, cfg.dy, cfg.dt, **kw).forward(
+        src, rec, wn, cfg.nt)
+    obs = obs.astype(np.float32)
+    rng = np.random.default_rng(12)
+    q = (float(np.abs(obs).max()) * rng.standard_normal(obs.shape)).astype(np.float32)
+
+    P = oracle.Problem(e0, s0, cfg.npml, cfg.dx, cfg.dy, cfg.dt, **kw)
+    otr, hists = P.forward(src, rec, wn, cfg.nt, keep_history=True)
+    oL = float(np.sum(q.astype(np.float64) * otr) + 0.5 * np.sum((otr - obs) ** 2))
+    oge, ogs, _ = P.adjoint(src, rec, q + (otr - obs), hists, cfg.nt)
+    del hists
+
+    w = torch.from_numpy(wn).cuda()
+    prob = AG.Problem(fwi.grid_from_config(cfg), src, rec, w)
+    et = torch.from_numpy(e0).cuda().requires_grad_(True)
+    st = torch.from_numpy(s0).cuda().requires_grad_(True)
+    tr = AG.traces(prob, et, st)
+    qt, ot = torch.from_numpy(q).cuda(), torch.from_numpy(obs).cuda()
+    loss = (qt.double() * tr.double()).sum() + 0.5 * ((tr.double() - ot.double()) ** 2).sum()
+    loss.backward()
+    errs = {"loss": abs(float(loss.detach()) - oL) / abs(oL),
+            "eps": rel_l2(et.grad.cpu().numpy(), oge), "sig": rel_l2(st.grad.cpu().numpy(), ogs)}
+    print("autograd vs oracle", errs, flush=True)
+    assert errs["loss"] <= 1e-4
+    assert errs["eps"] <= 1e-3 and errs["sig"] <= 1e-3
 
 
 def test_misfit_backward_scales_with_the_incoming_gradient(case):
