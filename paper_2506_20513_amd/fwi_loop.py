@@ -330,7 +330,9 @@ def main(argv=None):
     def rel(a, b):
         return float(torch.linalg.norm(a[sl] - b[sl]) / torch.linalg.norm(b[sl]))
 
-    out = {"workload": cfg.name, "bands_Hz": [b or 0 for b in bands], "iters_per_band": args.iters,
+    out = {"metric": "FWI wall-time to the final misfit", "value": round(r.seconds, 2),
+           "unit": "s", "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+           "workload": cfg.name, "bands_Hz": [b or 0 for b in bands], "iters_per_band": args.iters,
            "optimizer": st.optimizer, "tv_mode": st.tv_mode, "recipe": args.recipe,
            "tv_weight": args.tv, "evaluations": r.evaluations,
            "seconds": round(r.seconds, 2),
