@@ -176,11 +176,13 @@ def proposal_search(obj, x, f, g, d, t0=1.0, c1=0.1):
     quadratic through f(x), the slope and the first trial (within [0.05 t0,
     0.5 t0]).  Returns (result or None, suggested t0 for the next proposal):
     the quadratic's minimiser from the last trial, within [0.1, 4]."""
+    # cleared before any early return, so that a rejected proposal never
+    # reads as passed from an earlier call
+    obj.first_trial_passed = False
     gd = float(torch.dot(g, d))
     if gd >= 0:
         return None, t0
     t = t0
-    obj.first_trial_passed = False
     for trial in range(2):
         xn = obj.project(x + t * d)
         dec = float(torch.dot(g, xn - x))
@@ -263,7 +265,7 @@ def minimise(obj: Objective, iters: int, history: int = 10, first_step: float = 
             passed = False
             if d is not None:
                 res, t_net = proposal_search(obj, x, f, g, d, t0=t_net)
-                passed = getattr(obj, "first_trial_passed", False)
+                passed = res is not None and getattr(obj, "first_trial_passed", False)
                 dl = mem.direction(g)
                 if res is not None and passed and dl is not None:
                     # the L-BFGS step's own quadratic model predicts a decrease

@@ -110,6 +110,26 @@ def test_exact_proposal_is_accepted_and_bad_one_falls_back():
     assert all(it.source != "net" for it in bad.log)
 
 
+def test_ascent_proposals_after_a_good_one_are_struck():
+    """A proposer that is right once and then proposes ascent directions is
+    dropped after max_strikes proposals: the ascent proposals count as
+    strikes even though the good proposal before them passed."""
+    q = Quadratic(seed=6)
+    xm = q.constrained_min()
+    calls = []
+
+    def proposer(x, g):
+        calls.append(len(calls))
+        if len(calls) == 1:
+            return 0.5 * (xm - x)          # a good step, first trial passes
+        return g.clone()                    # ascent from then on
+
+    run = PC.minimise(q, 12, proposer=proposer, max_strikes=2)
+    assert run.log[1].source == "net"
+    assert len(calls) == 3, calls           # one good proposal, then two strikes
+    assert all(it.source != "net" for it in run.log[2:])
+
+
 def test_target_stops_the_run():
     q = Quadratic(seed=5)
     full = PC.minimise(q, 50)
