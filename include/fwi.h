@@ -249,7 +249,8 @@ const char *fwi_strerror(int status);
  * problems share one checkpoint interval) into one launch, and captures the
  * whole sequence in a HIP graph that each run replays.  For batches of
  * models too small to fill the GPU one at a time.  Results equal those of
- * fwi_gradient on each problem, bit for bit.
+ * fwi_gradient on each problem (bit for bit at the same temporal depth,
+ * see fwi_batch_plan_create).
  *
  * Ownership: the plan is a host object made by fwi_batch_plan_create and
  * released by fwi_batch_plan_destroy.  It keeps the device addresses of the
@@ -268,17 +269,28 @@ typedef struct fwi_batch_problem {
     float *grad_sigma;         /* device [NY][NX], overwritten                */
 } fwi_batch_problem;
 
+#define FWI_BATCH_MAX_TUNE 16
 typedef struct fwi_batch_info {
     int32_t nproblems;
     int32_t checkpoint_interval; /* common to all problems                   */
     int32_t band_rows;         /* row-band height in use (0: per-problem default) */
+    int32_t depth;             /* temporal depth of the passes (4 or 8)       */
     int32_t steps;             /* operations per run                          */
     int32_t stencil_launches;  /* merged stencil launches per run             */
     int32_t graph;             /* 1: runs replay a captured HIP graph         */
-    int32_t ntune;             /* band heights timed by the autotuner         */
-    int32_t tune_rows[8];      /* the heights (0: per-problem default)        */
-    double tune_ms[8];         /* first merged forward pass, best of 3, ms    */
+    int32_t ntune;             /* candidates timed by the autotuner           */
+    int32_t tune_depth[FWI_BATCH_MAX_TUNE]; /* each candidate's depth         */
+    int32_t tune_rows[FWI_BATCH_MAX_TUNE];  /* and band height (0: default)   */
+    double tune_ms[FWI_BATCH_MAX_TUNE];     /* its cost per time step, ms:
+                                  (2 x first merged forward pass + first
+                                  merged adjoint pass) / depth, best of 3   */
 } fwi_batch_info;
+
+/* `autotune` flags of fwi_batch_plan_create. */
+#define FWI_TUNE_BANDS 1       /* time row-band heights                       */
+#define FWI_TUNE_DEPTH 2       /* time temporal depths 4 and 8                */
+#define FWI_BATCH_DEPTH8 4     /* without FWI_TUNE_DEPTH: run at depth 8
+                                  (otherwise depth 4)                       */
 
 typedef struct fwi_batch_plan fwi_batch_plan;
 
@@ -289,10 +301,16 @@ int fwi_batch_workspace_bytes(int32_t nproblems, const fwi_batch_problem *proble
                               size_t *bytes);
 
 /* Validate, lay out the workspace, upload geometry and schedule tables,
- * optionally time candidate row-band heights (autotune != 0: runs stencil
- * passes on the workspace), and capture the graph.  Synchronises `stream`.
- * *plan receives the plan (NULL on error); FWI_ENOMEM if ws is missing,
- * misaligned or smaller than fwi_batch_workspace_bytes. */
+ * optionally time candidate temporal depths and row-band heights (autotune:
+ * FWI_TUNE_* flags; timing runs stencil passes on the workspace), and
+ * capture the graph.  Synchronises `stream`.  *plan receives the plan (NULL
+ * on error); FWI_ENOMEM if ws is missing, misaligned or smaller than
+ * fwi_batch_workspace_bytes; FWI_EINVAL for unknown flags.
+ * Results equal fwi_gradient's on each problem bit for bit when the plan
+ * runs at the temporal depth fwi_gradient uses for that problem (depth 4
+ * below 2^20 cells per shot, 8 from there on); at the other depth the
+ * per-pass partial sums of the imaging correlations group differently, and
+ * the results agree within FP32 rounding. */
 int fwi_batch_plan_create(int32_t nproblems, const fwi_batch_problem *problems, void *ws,
                           size_t ws_bytes, int32_t autotune, void *stream,
                           fwi_batch_plan **plan);

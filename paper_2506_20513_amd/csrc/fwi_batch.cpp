@@ -11,8 +11,9 @@
 // table-driven stencil kernels (every problem's arguments in a device
 // table), so small problems that could not fill the chip alone run side by
 // side.  The merged sequence is captured once in a HIP graph and replayed
-// by every run; the row-band height of the decomposition is chosen by
-// timing candidate heights on the first merged pass.
+// by every run; the temporal depth of the passes and the row-band height of
+// the decomposition are chosen by timing candidates on the first merged
+// forward and adjoint passes.
 #include "fwi_host.h"
 
 #include <algorithm>
@@ -55,6 +56,7 @@ struct Op {
 struct Step {
     OpKind kind;
     bool tail;
+    int depth;                     // temporal depth of a stencil step
     int nm;
     unsigned nblocks;
     size_t tab_off, boff_off;      // byte offsets in the workspace
@@ -71,12 +73,15 @@ struct Problem {
 
 hipError_t ok(int rc) { return rc == FWI_OK ? hipSuccess : hipErrorUnknown; }
 
-// Row bands of height `rows` (0 = the single-problem heuristic).
-void set_bands(Layout &L, int rows) {
+// Temporal depth of the passes and row bands of height `rows` (0 = the
+// single-problem heuristic for that depth).  The checkpoint interval is a
+// multiple of both depths, so the workspace layout does not change.
+void set_tiling(Layout &L, int depth, int rows) {
+    L.depth = depth;
     if (rows <= 0)
         make_tiling(L.d, L);
     else
-        fixed_bands(L, rows, kBatchDepth);
+        fixed_bands(L, rows, depth);
 }
 
 // The operations of one problem's gradient, in its own order, with keys.
@@ -95,6 +100,7 @@ void record(int ip, Problem &p, char *ws, std::vector<Op> &ops) {
     };
     const size_t field = (size_t)d.S * d.plane;
     const size_t fbytes = field * sizeof(float);
+    const int D = L.depth;
     float *Ca = P.f(L.off_Ca), *Cs = P.f(L.off_Cs);
     const State fs[2] = {P.state(L.off_fwd[0], false), P.state(L.off_fwd[1], false)};
     const State as[2] = {P.state(L.off_adj[0], true), P.state(L.off_adj[1], true)};
@@ -123,9 +129,9 @@ void record(int ip, Problem &p, char *ws, std::vector<Op> &ops) {
             hipError_t r = hipMemcpyAsync(cp, esrc, fbytes, hipMemcpyDeviceToDevice, st);
             return r == hipSuccess ? ok(copy_state(cst, fsrc, d, st)) : r;
         });
-        for (int n = n0; n < n1; n += kBatchDepth) {
+        for (int n = n0; n < n1; n += D) {
             a.n = n;
-            a.nlev = std::min(kBatchDepth, n1 - n);
+            a.nlev = std::min(D, n1 - n);
             a.E_in = P.slot(e);
             e ^= 1;
             a.E_out = P.slot(e);
@@ -177,9 +183,9 @@ void record(int ip, Problem &p, char *ws, std::vector<Op> &ops) {
         int fcur = 0, j = 0;
         FwdStreamArgs f = fwd_args(P);
         f.record = 0;
-        for (int n = n0; n < n1; n += kBatchDepth, ++j) {
+        for (int n = n0; n < n1; n += D, ++j) {
             f.n = n;
-            f.nlev = std::min(kBatchDepth, n1 - n);
+            f.nlev = std::min(D, n1 - n);
             f.E_in = P.slot(n - n0);
             f.E_lev = P.slot(n + 1 - n0);
             f.E_out = nullptr;
@@ -199,7 +205,7 @@ void record(int ip, Problem &p, char *ws, std::vector<Op> &ops) {
         j = 0;
         for (int n_top = n1; n_top > n0; n_top -= b.nlev, ++j) {
             // passes start at multiples of the depth, as in the single-problem sweep
-            b.nlev = n_top - std::max(n0, (n_top - 1) / kBatchDepth * kBatchDepth);
+            b.nlev = n_top - std::max(n0, (n_top - 1) / D * D);
             b.n_top = n_top;
             b.n_base = n0;
             b.E_lev = P.slot(0);
@@ -268,6 +274,7 @@ void build_schedule(std::vector<Problem> &probs, char *ws, size_t area, Schedule
             Step s;
             s.kind = OP_CALL;
             s.tail = false;
+            s.depth = 0;
             s.nm = 0;
             s.nblocks = 0;
             s.tab_off = s.boff_off = 0;
@@ -279,10 +286,12 @@ void build_schedule(std::vector<Problem> &probs, char *ws, size_t area, Schedule
         size_t j = i;
         while (j < ops.size() && ops[j].kind == o.kind && ops[j].key == o.key) ++j;
         // full-depth and partial passes go to separate launches
+        const int depth = o.kind == OP_FWD ? o.fa.tl.depth : o.aa.tl.depth;
         for (int tail = 0; tail < 2; ++tail) {
             Step s;
             s.kind = o.kind;
             s.tail = tail != 0;
+            s.depth = depth;
             s.nm = 0;
             s.nblocks = 0;
             s.boff_off = S.b_off + S.boff.size() * sizeof(unsigned);
@@ -292,7 +301,7 @@ void build_schedule(std::vector<Problem> &probs, char *ws, size_t area, Schedule
             for (size_t k = i; k < j; ++k) {
                 const Op &q = ops[k];
                 const int nlev = q.kind == OP_FWD ? q.fa.nlev : q.aa.nlev;
-                if ((nlev < kBatchDepth) != (tail != 0)) continue;
+                if ((nlev < depth) != (tail != 0)) continue;
                 const Tiling &tl = q.kind == OP_FWD ? q.fa.tl : q.aa.tl;
                 const int Sq = q.kind == OP_FWD ? q.fa.S : q.aa.S;
                 s.nblocks += stream_blocks(Sq, tl);
@@ -316,9 +325,9 @@ hipError_t run_step(const Step &s, char *ws, hipStream_t st) {
     const unsigned *boff = reinterpret_cast<const unsigned *>(ws + s.boff_off);
     if (s.kind == OP_FWD)
         return launch_fwd_table(reinterpret_cast<const FwdStreamArgs *>(ws + s.tab_off), boff,
-                                s.nm, s.nblocks, s.tail, st);
+                                s.nm, s.nblocks, s.depth, s.tail, st);
     return launch_adj_table(reinterpret_cast<const AdjStreamArgs *>(ws + s.tab_off), boff,
-                            s.nm, s.nblocks, s.tail, st);
+                            s.nm, s.nblocks, s.depth, s.tail, st);
 }
 
 int upload_tables(const Schedule &S, char *ws, hipStream_t st) {
@@ -358,11 +367,12 @@ int prepare(int32_t n, const fwi_batch_problem *pp, std::vector<Problem> &probs,
         p.u.geom.src_ij = p.src.data();
         p.u.geom.rec_ij = p.rec.data();
     }
-    // the interval minimising sum_m ceil(nt_m/K) C_m + (K+1) E_m
-    K = (int)std::lround(std::sqrt(num / den) / kBatchDepth) * kBatchDepth;
-    K = std::max(K, kBatchDepth);
+    // the interval minimising sum_m ceil(nt_m/K) C_m + (K+1) E_m, a
+    // multiple of both temporal depths so that either can run the plan
+    K = (int)std::lround(std::sqrt(num / den) / kDepthLarge) * kDepthLarge;
+    K = std::max(K, kDepthLarge);
     for (int i = 0; i < n; ++i) {
-        int rc = make_layout(probs[i].d, -1, probs[i].L, K, kBatchDepth);
+        int rc = make_layout(probs[i].d, -1, probs[i].L, K, kDepthSmall);
         if (rc != FWI_OK) return rc;
     }
     return FWI_OK;
@@ -389,6 +399,7 @@ struct fwi_batch_plan {
     char *ws = nullptr;
     int K = 0;
     int band_rows = 0;
+    int depth = kDepthSmall;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     fwi_batch_info info;
@@ -401,9 +412,10 @@ extern "C" int fwi_batch_workspace_bytes(int32_t n, const fwi_batch_problem *pro
     int K = 0;
     int rc = batch::prepare(n, problems, probs, K);
     if (rc != FWI_OK) return rc;
-    for (Problem &p : probs) set_bands(p.L, 0);
+    for (Problem &p : probs) set_tiling(p.L, kDepthSmall, 0);
     Schedule S;
-    // layout offsets do not change the table sizes: count with a null base
+    // layout offsets do not change the table sizes: count with a null base;
+    // depth 4 has the most passes, so its tables are the largest
     place(probs, 0);
     build_schedule(probs, nullptr, 0, S);
     *bytes = place(probs, S.bytes);
@@ -415,11 +427,12 @@ extern "C" int fwi_batch_plan_create(int32_t n, const fwi_batch_problem *problem
                                      fwi_batch_plan **out) {
     if (!out) return FWI_EINVAL;
     *out = nullptr;
+    if (autotune & ~(FWI_TUNE_BANDS | FWI_TUNE_DEPTH | FWI_BATCH_DEPTH8)) return FWI_EINVAL;
     std::vector<Problem> probs;
     int K = 0;
     int rc = batch::prepare(n, problems, probs, K);
     if (rc != FWI_OK) return rc;
-    for (Problem &p : probs) set_bands(p.L, 0);
+    for (Problem &p : probs) set_tiling(p.L, kDepthSmall, 0);
     Schedule S;
     place(probs, 0);
     build_schedule(probs, nullptr, 0, S);
@@ -456,11 +469,26 @@ extern "C" int fwi_batch_plan_create(int32_t n, const fwi_batch_problem *problem
         if (launch_profiles(p.d, P.prof(), st) != hipSuccess) return fail(FWI_EHIP);
     }
 
-    // band height: time the first merged forward pass for candidate heights
-    int rows = 0;
-    if (autotune) {
-        const int cand[] = {0, 32, 64, 128, 256, 512, 1 << 20};
-        const int ncand = (int)(sizeof(cand) / sizeof(cand[0]));
+    // candidates: temporal depth x row-band height
+    std::vector<int> depths, heights;
+    if (autotune & FWI_TUNE_DEPTH) {
+        depths = {kDepthSmall, kDepthLarge};
+    } else {
+        depths = {(autotune & FWI_BATCH_DEPTH8) ? kDepthLarge : kDepthSmall};
+    }
+    if (autotune & FWI_TUNE_BANDS)
+        heights = {0, 32, 64, 128, 256, 512, 1 << 20};
+    else
+        heights = {0};
+    int depth = depths[0], rows = heights[0];
+    if (depths.size() * heights.size() > 1) {
+        // time the first merged forward pass and the first merged adjoint
+        // pass of every candidate (best of 3 each); a gradient runs two
+        // forward passes (sweep and segment re-forward) and one adjoint pass
+        // per `depth` steps, so the cost per step is (2 fwd + adj) / depth.
+        // The adjoint pass runs on whatever state the workspace holds (all of
+        // it allocated); its time does not depend on the values, and every
+        // run of the plan clears that state first.
         double best = 1e300;
         hipEvent_t e0, e1;
         if (hipEventCreate(&e0) != hipSuccess) return fail(FWI_EHIP);
@@ -468,50 +496,64 @@ extern "C" int fwi_batch_plan_create(int32_t n, const fwi_batch_problem *problem
             (void)hipEventDestroy(e0);
             return fail(FWI_EHIP);
         }
-        int tuned = 0;
-        for (int ci = 0; ci < ncand && rc == FWI_OK; ++ci) {
-            for (Problem &p : probs) set_bands(p.L, cand[ci]);
-            rc = upload_all();
-            if (rc != FWI_OK) break;
-            build_schedule(probs, w, 0, S);
-            rc = upload_tables(S, w, st);
-            if (rc != FWI_OK) break;
-            // run the set-up steps once so the first pass reads valid state
-            size_t first = 0;
-            while (first < S.steps.size() && S.steps[first].kind == OP_CALL) {
-                if (run_step(S.steps[first], w, st) != hipSuccess) rc = FWI_EHIP;
-                ++first;
-            }
-            if (rc != FWI_OK || first >= S.steps.size()) break;
-            float ms_min = 1e30f;
-            for (int rep = 0; rep < 3 && rc == FWI_OK; ++rep) {
-                if (hipEventRecord(e0, st) != hipSuccess ||
-                    run_step(S.steps[first], w, st) != hipSuccess ||
-                    hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-                    rc = FWI_EHIP;
-                    break;
-                }
+        auto time_step = [&](const Step &s, float &ms_min) -> int {
+            ms_min = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) {
+                if (hipEventRecord(e0, st) != hipSuccess || run_step(s, w, st) != hipSuccess ||
+                    hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+                    return FWI_EHIP;
                 float ms = 0.f;
-                if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = FWI_EHIP;
+                if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return FWI_EHIP;
                 ms_min = std::min(ms_min, ms);
             }
+            return FWI_OK;
+        };
+        int tuned = 0;
+        for (int dep : depths) {
+            for (int h : heights) {
+                for (Problem &p : probs) set_tiling(p.L, dep, h);
+                rc = upload_all();
+                if (rc != FWI_OK) break;
+                build_schedule(probs, w, 0, S);
+                rc = upload_tables(S, w, st);
+                if (rc != FWI_OK) break;
+                // run the set-up steps once so the first pass reads valid state
+                size_t first = 0;
+                while (first < S.steps.size() && S.steps[first].kind == OP_CALL) {
+                    if (run_step(S.steps[first], w, st) != hipSuccess) rc = FWI_EHIP;
+                    ++first;
+                }
+                size_t fadj = first;
+                while (fadj < S.steps.size() && S.steps[fadj].kind != OP_ADJ) ++fadj;
+                if (rc != FWI_OK || first >= S.steps.size() || fadj >= S.steps.size()) {
+                    rc = rc == FWI_OK ? FWI_EHIP : rc;
+                    break;
+                }
+                float tf = 0.f, ta = 0.f;
+                rc = time_step(S.steps[first], tf);
+                if (rc == FWI_OK) rc = time_step(S.steps[fadj], ta);
+                if (rc != FWI_OK) break;
+                const double cost = (2.0 * tf + ta) / dep;
+                if (tuned < FWI_BATCH_MAX_TUNE) {
+                    plan->info.tune_depth[tuned] = dep;
+                    plan->info.tune_rows[tuned] = h;
+                    plan->info.tune_ms[tuned] = cost;
+                    ++tuned;
+                }
+                if (cost < best * 0.98) {
+                    best = cost;
+                    depth = dep;
+                    rows = h;
+                }
+            }
             if (rc != FWI_OK) break;
-            if (tuned < 8) {
-                plan->info.tune_rows[tuned] = cand[ci];
-                plan->info.tune_ms[tuned] = ms_min;
-                ++tuned;
-            }
-            if (ms_min < best * 0.98) {
-                best = ms_min;
-                rows = cand[ci];
-            }
         }
         plan->info.ntune = tuned;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (rc != FWI_OK) return fail(rc);
     }
-    for (Problem &p : probs) set_bands(p.L, rows);
+    for (Problem &p : probs) set_tiling(p.L, depth, rows);
     rc = upload_all();
     if (rc != FWI_OK) return fail(rc);
     build_schedule(probs, w, 0, S);
@@ -546,9 +588,11 @@ extern "C" int fwi_batch_plan_create(int32_t n, const fwi_batch_problem *problem
     plan->probs = std::move(probs);
     plan->sched = std::move(S);
     plan->band_rows = rows;
+    plan->depth = depth;
     plan->info.nproblems = n;
     plan->info.checkpoint_interval = K;
     plan->info.band_rows = rows;
+    plan->info.depth = depth;
     plan->info.steps = (int32_t)plan->sched.steps.size();
     plan->info.stencil_launches = plan->sched.stencil_launches;
     plan->info.graph = captured ? 1 : 0;

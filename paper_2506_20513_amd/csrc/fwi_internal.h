@@ -89,12 +89,11 @@ struct Layout {
 // 2088x1064 grid with 64 shots (300 against 207 G/s), and was 12-38% slower
 // on grids of 0.02-0.25 M cells, where the longer pipeline start of every
 // band weighs more.  A problem uses depth 8 from kDepthLargeCells cells per
-// shot on.  Batched problems always use depth 4 (one depth for all merged
-// passes).
+// shot on.  A batch of problems runs all its merged passes at one depth:
+// depth 4 unless its plan's autotuner (or its caller) picks depth 8.
 constexpr int kDepthSmall = 4;
 constexpr int kDepthLarge = 8;
 constexpr long long kDepthLargeCells = 1LL << 20;
-constexpr int kBatchDepth = kDepthSmall;
 
 // Source and receiver tables on the device.  Receivers of each shot are
 // sorted by (row, column), stable in receiver index; rrow is the row CSR.
@@ -190,10 +189,12 @@ hipError_t launch_adj_stream(const AdjStreamArgs &a, hipStream_t st);
 unsigned stream_blocks(int S, const Tiling &tl);
 // One pass for nm problems at once: tab[m] (device) holds problem m's
 // arguments and boff[0..nm] (device) the prefix sums of their block counts,
-// nblocks = boff[nm].  tail: some problem advances fewer than kBatchDepth levels.
+// nblocks = boff[nm].  depth: the passes' temporal depth (kDepthSmall or
+// kDepthLarge, the same for every problem of the launch); tail: the
+// problems advance fewer than depth levels.
 hipError_t launch_fwd_table(const FwdStreamArgs *tab, const unsigned *boff, int nm,
-                            unsigned nblocks, bool tail, hipStream_t st);
+                            unsigned nblocks, int depth, bool tail, hipStream_t st);
 hipError_t launch_adj_table(const AdjStreamArgs *tab, const unsigned *boff, int nm,
-                            unsigned nblocks, bool tail, hipStream_t st);
+                            unsigned nblocks, int depth, bool tail, hipStream_t st);
 
 }  // namespace fwi

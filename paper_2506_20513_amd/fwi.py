@@ -92,18 +92,27 @@ class fwi_batch_problem(ctypes.Structure):
                 ("grad_eps_r", ctypes.c_void_p), ("grad_sigma", ctypes.c_void_p)]
 
 
+BATCH_MAX_TUNE = 16
+FWI_TUNE_BANDS = 1
+FWI_TUNE_DEPTH = 2
+FWI_BATCH_DEPTH8 = 4
+
+
 class fwi_batch_info(ctypes.Structure):
     _fields_ = [("nproblems", ctypes.c_int32), ("checkpoint_interval", ctypes.c_int32),
-                ("band_rows", ctypes.c_int32), ("steps", ctypes.c_int32),
-                ("stencil_launches", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("ntune", ctypes.c_int32), ("tune_rows", ctypes.c_int32 * 8),
-                ("tune_ms", ctypes.c_double * 8)]
+                ("band_rows", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("steps", ctypes.c_int32), ("stencil_launches", ctypes.c_int32),
+                ("graph", ctypes.c_int32), ("ntune", ctypes.c_int32),
+                ("tune_depth", ctypes.c_int32 * BATCH_MAX_TUNE),
+                ("tune_rows", ctypes.c_int32 * BATCH_MAX_TUNE),
+                ("tune_ms", ctypes.c_double * BATCH_MAX_TUNE)]
 
     def as_dict(self):
         return {"nproblems": self.nproblems, "checkpoint_interval": self.checkpoint_interval,
-                "band_rows": self.band_rows, "steps": self.steps,
+                "band_rows": self.band_rows, "depth": self.depth, "steps": self.steps,
                 "stencil_launches": self.stencil_launches, "graph": bool(self.graph),
-                "tuning": [(self.tune_rows[k], self.tune_ms[k]) for k in range(self.ntune)]}
+                "tuning": [(self.tune_depth[k], self.tune_rows[k], self.tune_ms[k])
+                           for k in range(self.ntune)]}
 
 
 def lib() -> ctypes.CDLL:
@@ -336,12 +345,20 @@ class BatchPlan:
     stream); close() releases the plan."""
 
     def __init__(self, problems, ws, autotune=True, stream=None):
+        """autotune: True (time temporal depths and band heights), False
+        (depth 4, default bands) or FWI_TUNE_* / FWI_BATCH_DEPTH8 flags."""
+        if autotune is True:
+            flags = FWI_TUNE_BANDS | FWI_TUNE_DEPTH
+        elif autotune is False or autotune is None:
+            flags = 0
+        else:
+            flags = int(autotune)
         self.problems = list(problems)
         self.ws = ws
         self._arr = _batch_array(self.problems)
         h = ctypes.c_void_p()
         _check(lib().fwi_batch_plan_create(len(self.problems), self._arr, _wsptr(ws),
-                                           _nbytes(ws), int(bool(autotune)), _stream(stream),
+                                           _nbytes(ws), flags, _stream(stream),
                                            ctypes.byref(h)), "fwi_batch_plan_create")
         self._h = h
 

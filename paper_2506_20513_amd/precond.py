@@ -621,20 +621,61 @@ def train(ds, epochs: int, batch: int = 32, lr: float = 1e-3, seed: int = 0,
     return net, hist
 
 
+def minimise_wolfe(obj: Objective, iters: int, history: int = 10, log=None) -> Run:
+    """The inversion driver's plain method on the same objective: torch's
+    L-BFGS with a strong-Wolfe line search (as fwi_loop.invert runs it),
+    `iters` iterations, on the projected point (surface rows fixed, bounds
+    clamped).  The final objective is evaluated once more at the projected
+    last iterate, outside the timed region."""
+    sync = (lambda: torch.cuda.synchronize()) if obj.x0.is_cuda else (lambda: None)
+    sync()
+    t0 = time.perf_counter()
+    x = obj.project(obj.x0).clone().requires_grad_(True)
+    opt = torch.optim.LBFGS([x], lr=1.0, max_iter=iters, history_size=history,
+                            line_search_fn="strong_wolfe", tolerance_grad=1e-12,
+                            tolerance_change=1e-12)
+    run = Run()
+
+    def closure():
+        opt.zero_grad()
+        f, g = obj(obj.project(x.detach()))
+        x.grad = g.clone()
+        if log:
+            log(f"  wolfe evaluation {obj.evals}: f {f:.6g}, {time.perf_counter() - t0:.2f} s")
+        return torch.tensor(f, dtype=x.dtype, device=x.device)
+
+    opt.step(closure)
+    sync()
+    seconds = time.perf_counter() - t0
+    evals = obj.evals
+    xf = obj.project(x.detach())
+    f, _ = obj(xf)
+    obj.evals = evals
+    run.log.append(Iterate(iters, f, obj.last_J, evals, seconds, "lbfgs-wolfe"))
+    run.seconds = seconds
+    run.x = xf
+    return run
+
+
 def compare(net: nn.Net, problems, iters: int, st: FL.Settings, log=print,
-            verbose: bool = False) -> list:
+            verbose: bool = False, plain_method: str = "armijo") -> list:
     """Plain L-BFGS for `iters` iterations, then the learned variant until it
     reaches the plain run's final objective (at most 2 iters iterations).
-    Returns one record per problem with both wall-clock times.  verbose:
-    log every iterate."""
+    plain_method: "armijo" (this module's projected L-BFGS, the learned
+    run's own fallback) or "wolfe" (the inversion driver's strong-Wolfe
+    L-BFGS).  Returns one record per problem with both wall-clock times.
+    verbose: log every iterate."""
     out = []
     for item in problems:
         name, prob, obs, e0, s0 = item[:5]
         factor = item[5] if len(item) > 5 else 1
         obj = Objective(prob, obs, e0, s0, st)
         if verbose and log:
-            log(f"{name}: plain L-BFGS")
-        plain = minimise(obj, iters, log=log if verbose else None)
+            log(f"{name}: plain L-BFGS ({plain_method})")
+        if plain_method == "wolfe":
+            plain = minimise_wolfe(obj, iters, log=log if verbose else None)
+        else:
+            plain = minimise(obj, iters, log=log if verbose else None)
         target = plain.final_f
         objn = Objective(prob, obs, e0, s0, st)
         pc = Preconditioner(net, factor)
@@ -643,7 +684,8 @@ def compare(net: nn.Net, problems, iters: int, st: FL.Settings, log=print,
         learned = minimise(objn, 2 * iters, proposer=lambda x, g: pc(objn, x, g),
                            target_f=target, log=log if verbose else None)
         reached = learned.final_f <= target
-        rec = {"problem": name, "plain_seconds": round(plain.seconds, 3),
+        rec = {"problem": name, "plain_method": plain_method,
+               "plain_seconds": round(plain.seconds, 3),
                "plain_evaluations": obj.evals, "plain_final_f": target,
                "plain_final_rel_misfit": plain.log[-1].J / obj.J0,
                "learned_seconds": round(learned.seconds, 3),
@@ -705,6 +747,9 @@ def main(argv=None):
     ap.add_argument("--survey-pair-iters", type=int, default=10)
     ap.add_argument("--load", default=None,
                     help="trained parameters (.npy) to use instead of generating and training")
+    ap.add_argument("--plain", default="armijo", choices=["armijo", "wolfe"],
+                    help="plain method the learned run must match: this module's projected "
+                         "L-BFGS (armijo) or the inversion driver's strong-Wolfe L-BFGS (wolfe)")
     args = ap.parse_args(argv)
     if not torch.cuda.is_available():
         print("precond: no GPU visible", file=sys.stderr)
@@ -737,22 +782,21 @@ def main(argv=None):
     for k in range(args.eval):
         cfg, prob, obs, e, s, e0, s0 = tiny_problem(50000 + k, 6.0)
         problems.append((f"tiny-128x128-seed{50000 + k}", prob, obs, e0, s0))
-    res = compare(net, problems, args.iters, st, log=err)
-    out["compare"] = res
-    out["summary"] = _summary(res)
+    if problems:
+        res = compare(net, problems, args.iters, st, log=err, plain_method=args.plain)
+        out["compare"] = res
+        out["summary"] = _summary(res)
     del problems
     from . import inputs as I
     if args.survey:
         r = compare(net, [_survey_problem(I.config_survey(), args.factor)], args.survey_iters, st,
-                    log=err,
-                    verbose=True)
+                    log=err, verbose=True, plain_method=args.plain)
         out["compare_survey"] = r
     if args.large:
         torch.cuda.empty_cache()
         err("large: building the problem (observed traces)")
         r = compare(net, [_survey_problem(I.config_large(), args.factor)], args.large_iters, st,
-                    log=err,
-                    verbose=True)
+                    log=err, verbose=True, plain_method=args.plain)
         out["compare_large"] = r
     print(json.dumps(out), flush=True)
     return 0

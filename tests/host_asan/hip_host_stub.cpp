@@ -98,11 +98,11 @@ hipError_t launch_adj_stream(const AdjStreamArgs &a, hipStream_t) {
     return a.nlev >= 1 && a.nlev <= a.tl.depth ? hipSuccess : hipErrorInvalidValue;
 }
 unsigned stream_blocks(int S, const Tiling &tl) { return (unsigned)S * tl.nstrip * tl.nband; }
-hipError_t launch_fwd_table(const FwdStreamArgs *, const unsigned *, int, unsigned, bool,
+hipError_t launch_fwd_table(const FwdStreamArgs *, const unsigned *, int, unsigned, int, bool,
                             hipStream_t) {
     return hipSuccess;
 }
-hipError_t launch_adj_table(const AdjStreamArgs *, const unsigned *, int, unsigned, bool,
+hipError_t launch_adj_table(const AdjStreamArgs *, const unsigned *, int, unsigned, int, bool,
                             hipStream_t) {
     return hipSuccess;
 }

@@ -121,6 +121,7 @@ def main():
     geos = [I.geometry(cfgs[0]), (s2, r2), I.geometry(cfgs[2])]
     run_batch(cfgs, geos, autotune=True)
     run_batch(cfgs, geos, autotune=False)
+    run_batch(cfgs, geos, autotune=fwi.FWI_BATCH_DEPTH8)
     for p in held:
         libc.free(p)
     print("host paths ok", flush=True)

@@ -5,7 +5,9 @@ for bit: same per-cell arithmetic, and checkpoint re-forward equals stored
 history for any interval); the captured graph replays the same results run
 after run, with eager work in between; the result does not depend on the
 autotuned band height; models updated in place are picked up by the next
-run.  One problem is also checked against the FP64 oracle.
+run.  At temporal depth 8 (forced, or chosen by the autotuner over depth
+and band height) the results agree within FP32 rounding.  Problems are also
+checked against the FP64 oracle, with the oracle's own observed data.
 """
 import numpy as np
 import pytest
@@ -74,7 +76,7 @@ class Case:
         return float(self.mis.item()), np_(self.ge), np_(self.gs)
 
 
-def make_plan(cases, autotune=True):
+def make_plan(cases, autotune=fwi.FWI_TUNE_BANDS):
     probs = [c.problem() for c in cases]
     ws = fwi.alloc_workspace(fwi.batch_workspace_bytes(probs))
     return fwi.BatchPlan(probs, ws, autotune=autotune)
@@ -151,17 +153,78 @@ def test_updated_model_is_used_by_the_next_run(batch):
         c0.e0.copy_(saved)
 
 
-def test_one_batched_problem_against_the_oracle(batch):
-    import torch
-    c = batch["cases"][1]
+def _oracle_problem(c, eps, sig):
     cfg = c.cfg
-    batch["plan"].run()
+    return oracle.Problem(eps, sig, cfg.npml, cfg.dx, cfg.dy, cfg.dt, cpml_order=cfg.cpml_order,
+                          cpml_sigma_scale=cfg.cpml_sigma_scale,
+                          cpml_kappa_max=cfg.cpml_kappa_max, cpml_alpha_max=cfg.cpml_alpha_max)
+
+
+def _against_oracle(plan, c):
+    """Run `plan` with case c's observed data replaced by the oracle's
+    forward of its true model (restored afterwards), and compare c's misfit
+    and gradients with the oracle's gradient for the same data."""
+    import torch
+    cfg = c.cfg
+    w = np_(c.w)
+    obs_o, _ = _oracle_problem(c, np_(c.e), np_(c.s)).forward(c.src, c.rec, w, cfg.nt)
+    obs_o = obs_o.astype(np.float32)
+    J, oge, ogs, _ = _oracle_problem(c, np_(c.e0), np_(c.s0)).gradient(c.src, c.rec, w, obs_o,
+                                                                      cfg.nt)
+    saved = c.obs.clone()
+    try:
+        c.obs.copy_(torch.from_numpy(obs_o))
+        plan.run()
+        torch.cuda.synchronize()
+        mis, ge, gs = c.result()
+    finally:
+        c.obs.copy_(saved)
+    errs = (abs(mis - J) / J, rel_l2(ge, oge), rel_l2(gs, ogs))
+    print(c.cfg.name, "against the oracle: misfit, grad eps, grad sigma", errs, flush=True)
+    assert errs[0] <= 1e-4 and errs[1] <= 1e-3 and errs[2] <= 1e-3
+
+
+def test_one_batched_problem_against_the_oracle(batch):
+    _against_oracle(batch["plan"], batch["cases"][1])
+
+
+def test_depth8_batch(batch):
+    """The same batch at temporal depth 8 (FWI_BATCH_DEPTH8): within FP32
+    rounding of the depth-4 single-problem gradients (the imaging sums group
+    by 8 steps instead of 4), and one problem against the oracle."""
+    import torch
+    plan = make_plan(batch["cases"], autotune=fwi.FWI_BATCH_DEPTH8)
+    info = plan.info()
+    assert info["depth"] == 8 and info["graph"], info
+    plan.run()
     torch.cuda.synchronize()
-    P = oracle.Problem(np_(c.e0), np_(c.s0), cfg.npml, cfg.dx, cfg.dy, cfg.dt,
-                       cpml_order=cfg.cpml_order, cpml_sigma_scale=cfg.cpml_sigma_scale,
-                       cpml_kappa_max=cfg.cpml_kappa_max, cpml_alpha_max=cfg.cpml_alpha_max)
-    J, oge, ogs, _ = P.gradient(c.src, c.rec, np_(c.w), np_(c.obs), cfg.nt)
-    mis, ge, gs = c.result()
-    print("oracle misfit", J, "gpu", mis, "grad rel L2", rel_l2(ge, oge), rel_l2(gs, ogs), flush=True)
-    assert abs(mis - J) <= 1e-4 * J
-    assert rel_l2(ge, oge) <= 1e-3 and rel_l2(gs, ogs) <= 1e-3
+    for c, ref in zip(batch["cases"], batch["refs"]):
+        mis, ge, gs = c.result()
+        errs = (abs(mis - ref[0]) / ref[0], rel_l2(ge, ref[1]), rel_l2(gs, ref[2]))
+        print(c.cfg.name, "depth 8 vs depth 4", errs, flush=True)
+        assert errs[0] <= 1e-6 and errs[1] <= 1e-5 and errs[2] <= 1e-5, errs
+    _against_oracle(plan, batch["cases"][3])
+    plan.close()
+
+
+def test_autotuner_over_depth_and_bands(batch):
+    """The full autotuner times both depths with every band height and runs
+    the cheapest; bit for bit the single-problem results at depth 4, within
+    rounding at depth 8."""
+    import torch
+    plan = make_plan(batch["cases"], autotune=True)
+    info = plan.info()
+    print("autotuned plan", info, flush=True)
+    depths = sorted({d for d, _, _ in info["tuning"]})
+    assert depths == [4, 8] and len(info["tuning"]) == 14
+    best = min(info["tuning"], key=lambda t: t[2])
+    assert (info["depth"], info["band_rows"]) == (best[0], best[1])
+    plan.run()
+    torch.cuda.synchronize()
+    for c, ref in zip(batch["cases"], batch["refs"]):
+        got = c.result()
+        if info["depth"] == 4:
+            assert same(got, ref), c.cfg.name
+        else:
+            assert rel_l2(got[1], ref[1]) <= 1e-5 and rel_l2(got[2], ref[2]) <= 1e-5
+    plan.close()

@@ -227,7 +227,7 @@ def test_few_steps(nt):
 def test_survey_sampled_shots():
     """512x256 / 24 shots / 3000 steps, all shots batched in one sweep on the
     GPU; the oracle recomputes shots 0 and 23 one by one for the traces, and
-    the gradient of shot 0 alone."""
+    the gradient of shot 0 alone (observed data: the oracle's shot-0 traces)."""
     cfg = I.config_survey()
     e, s, e0, s0 = I.model_for(cfg)
     src, rec = I.geometry(cfg)
@@ -236,13 +236,17 @@ def test_survey_sampled_shots():
     tr, _ = run.forward()
     tr = np_(tr)
     P = oracle_problem(cfg, e, s)
+    otr0 = None
     for k in (0, cfg.nshots - 1):
         otr, _ = P.forward(src[k:k + 1], rec[k:k + 1], w[k:k + 1], cfg.nt)
         err = rel_l2(tr[k], otr[0])
         print("shot", k, "traces rel L2", err, flush=True)
         assert err <= TR_TOL
-    # gradient of shot 0 on the smoothed model
-    obs0 = tr[0:1]
+        if k == 0:
+            otr0 = otr
+    # gradient of shot 0 on the smoothed model, against the oracle's own
+    # traces of the true model as observed data
+    obs0 = otr0.astype(np.float32)
     P0 = oracle_problem(cfg, e0, s0)
     J, oge, ogs, _ = P0.gradient(src[:1], rec[:1], w[:1], obs0, cfg.nt)
     mis, ge, gs, _ = Run(fwi.grid_from_config(cfg), src[:1], rec[:1], w[:1], e0, s0).gradient(obs0)

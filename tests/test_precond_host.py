@@ -130,6 +130,20 @@ def test_ascent_proposals_after_a_good_one_are_struck():
     assert all(it.source != "net" for it in run.log[2:])
 
 
+def test_strong_wolfe_plain_run_minimises_and_keeps_fixed_coordinates():
+    """The driver's strong-Wolfe L-BFGS on the same objective interface
+    (the plain method of the comparison) converges on the quadratic, keeps
+    the fixed coordinates and reports its final objective."""
+    q = Quadratic(seed=7)
+    run = PC.minimise_wolfe(q, 60)
+    xm = q.constrained_min()
+    r = xm - q.xs
+    fmin = 0.5 * float(r @ q.A @ r)
+    assert run.final_f - fmin <= 1e-8 * q.J0
+    assert torch.equal(run.x[:3], q.x0[:3])
+    assert run.log[-1].evals == q.evals and run.log[-1].evals >= 60
+
+
 def test_target_stops_the_run():
     q = Quadratic(seed=5)
     full = PC.minimise(q, 50)
