@@ -260,12 +260,14 @@ __global__ void k_flip(const bf16 *__restrict__ w, bf16 *__restrict__ wf, int Ci
 // Weight and bias gradients: dw[co][ky][kx][ci] = sum_q dz[q][co] x[q + (ky-1, kx-1)][ci],
 // db[co] = sum_q dz[q][co].  A GEMM whose reduction runs over output pixels
 // q: a block owns a 32 (co) x 32 (ci) tile for all nine taps, loops over
-// every gridDim.x-th chunk of 32 pixels and writes its partial sums to
+// every gridDim.x-th chunk of CH pixels and writes its partial sums to
 // part[blockIdx.x].
 //
-// Per chunk q0 .. q0+31 the block stages, in natural (pixel-major) layout:
-//   Z[j][c]      = dz[q0 + j][co tile]                          (32 rows)
-//   X[ky][j][c]  = x[q0 - 1 + j + (ky-1) W][ci tile]             (34 rows)
+// Per chunk q0 .. q0+CH-1 the block stages, in natural (pixel-major) layout:
+//   Z[j][c]      = dz[q0 + j][co tile]                          (CH rows)
+//   X[ky][j][c]  = x[q0 - 1 + j + (ky-1) W][ci tile]             (CH + 2 rows)
+// and each wave runs nine MFMAs per 32 pixels of the chunk.  Chunks of 64
+// pixels halve the barriers and staging rounds per MFMA against 32.
 // X rows are zero where the row of q = q0 - 1 + j plus ky - 1 leaves the
 // image (or q is outside 0 .. P-1).  A tap (ky, kx) reads X[ky] from row kx
 // on, so the three kx taps share one staged tile; the taps that would wrap
@@ -279,6 +281,7 @@ __global__ void k_flip(const bf16 *__restrict__ w, bf16 *__restrict__ wf, int Ci
 // i/4+12; so with lane s of the group reading row base + s/4 at channel
 // 4 (s % 4), lane i gets channel i at rows base .. base + 3.
 constexpr int kWP = 40;     // LDS row pitch in bf16: 32 channels + 8 padding
+constexpr int kWgradChunk = 64;   // pixels staged per step of k_wgrad
 
 typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 typedef __attribute__((address_space(3))) bf16x4 *lds_bf16x4_ptr;
@@ -294,18 +297,22 @@ __device__ __forceinline__ bf16x8 tr_fragment(const bf16 *tile, int base, int h,
     return bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
 }
 
+template <int CH>
 __global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ x,
                                                const bf16 *__restrict__ dz,
                                                float *__restrict__ part,
                                                float *__restrict__ bpart, int N, int H, int W,
                                                int Ci, int Co) {
-    __shared__ __attribute__((aligned(16))) bf16 Z[32 * kWP];
-    __shared__ __attribute__((aligned(16))) bf16 X[3][34 * kWP];
+    static_assert(CH % 32 == 0, "chunks of whole 32-pixel fragments");
+    constexpr int NH = CH / 32;                   // 32-pixel halves per chunk
+    constexpr int XR = CH + 2;                    // staged X rows per ky
+    __shared__ __attribute__((aligned(16))) bf16 Z[CH * kWP];
+    __shared__ __attribute__((aligned(16))) bf16 X[3][XR * kWP];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = threadIdx.x;
     const int nci = Ci / 32;
     const int cit = blockIdx.y % nci, cot = blockIdx.y / nci;
     const int64_t P = (int64_t)N * H * W;
-    const int64_t nchunk = (P + 31) / 32;
+    const int64_t nchunk = (P + CH - 1) / CH;
     const int mt = wave >> 1, nt = wave & 1;      // this wave's 16 x 16 sub-tile
     const int g = lane >> 4;                      // pixel group: rows 8 g .. 8 g + 7
     f32x4 acc[9];
@@ -314,24 +321,26 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ x,
     float bsum = 0.f;                               // bias partial (ci tile 0)
     const bool do_bias = cit == 0;
     const bf16 zero = (bf16)0.f;
-    // staging: 32 x 4 pieces of Z, then 3 x 34 x 4 pieces of X (16 bytes
-    // each), at most three per thread; the pieces of the next chunk are
-    // loaded into registers while the current chunk computes
-    constexpr int kPieces = 32 * 4 + 3 * 34 * 4;
-    uint4 pre[3];
+    // staging: CH x 4 pieces of Z, then 3 x (CH + 2) x 4 pieces of X (16
+    // bytes each), kPer per thread; the pieces of the next chunk are loaded
+    // into registers while the current chunk computes
+    constexpr int kZ = CH * 4;
+    constexpr int kPieces = kZ + 3 * XR * 4;
+    constexpr int kPer = (kPieces + 255) / 256;
+    uint4 pre[kPer];
     auto fetch = [&](int64_t q0, uint4 *out) {
         const int col0 = (int)(q0 % W), row0 = (int)((q0 / W) % H);
 #pragma unroll
-        for (int u = 0; u < 3; ++u) {
+        for (int u = 0; u < kPer; ++u) {
             const int idx = t + 256 * u;
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (idx < 128) {
+            if (idx < kZ) {
                 const int j = idx >> 2, c = (idx & 3) * 8;
                 const int64_t q = q0 + j;
                 if (q < P) v = *reinterpret_cast<const uint4 *>(dz + q * Co + cot * 32 + c);
             } else if (idx < kPieces) {
-                const int r = idx - 128;
-                const int ky = r / (34 * 4), j = (r >> 2) % 34, c = (r & 3) * 8;
+                const int r = idx - kZ;
+                const int ky = r / (XR * 4), j = (r >> 2) % XR, c = (r & 3) * 8;
                 const int64_t q = q0 - 1 + j;
                 if (q >= 0 && q < P) {
                     const int d = col0 - 1 + j;                 // >= -1
@@ -345,46 +354,50 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ x,
             out[u] = v;
         }
     };
-    if ((int64_t)blockIdx.x < nchunk) fetch((int64_t)blockIdx.x * 32, pre);
+    if ((int64_t)blockIdx.x < nchunk) fetch((int64_t)blockIdx.x * CH, pre);
     for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
-        const int64_t q0 = ch * 32;
+        const int64_t q0 = ch * CH;
         const int col0 = (int)(q0 % W);
         __syncthreads();   // previous chunk's reads done
 #pragma unroll
-        for (int u = 0; u < 3; ++u) {
+        for (int u = 0; u < kPer; ++u) {
             const int idx = t + 256 * u;
-            if (idx < 128) {
+            if (idx < kZ) {
                 *reinterpret_cast<uint4 *>(&Z[(idx >> 2) * kWP + (idx & 3) * 8]) = pre[u];
             } else if (idx < kPieces) {
-                const int r = idx - 128;
-                *reinterpret_cast<uint4 *>(&X[r / (34 * 4)][((r >> 2) % 34) * kWP + (r & 3) * 8]) =
+                const int r = idx - kZ;
+                *reinterpret_cast<uint4 *>(&X[r / (XR * 4)][((r >> 2) % XR) * kWP + (r & 3) * 8]) =
                     pre[u];
             }
         }
         __syncthreads();
-        if (ch + gridDim.x < nchunk) fetch((ch + gridDim.x) * 32, pre);
-        // dz fragment (channels 16 mt .. +15, pixels 8 g .. 8 g + 7) and its
-        // two edge-masked copies
-        const bf16x8 a1 = tr_fragment(Z, 8 * g, mt, lane);
-        bf16x8 a0 = a1, a2 = a1;
+        if (ch + gridDim.x < nchunk) fetch((ch + gridDim.x) * CH, pre);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int col = (col0 + 8 * g + e) % W;
-            if (col == 0) a0[e] = zero;
-            if (col == W - 1) a2[e] = zero;
-        }
+        for (int hf = 0; hf < NH; ++hf) {
+            // dz fragment (channels 16 mt .. +15, pixels 32 hf + 8 g .. +7)
+            // and its two edge-masked copies
+            const int pb = 32 * hf + 8 * g;
+            const bf16x8 a1 = tr_fragment(Z, pb, mt, lane);
+            bf16x8 a0 = a1, a2 = a1;
 #pragma unroll
-        for (int ky = 0; ky < 3; ++ky) {
+            for (int e = 0; e < 8; ++e) {
+                const int col = (col0 + pb + e) % W;
+                if (col == 0) a0[e] = zero;
+                if (col == W - 1) a2[e] = zero;
+            }
 #pragma unroll
-            for (int kx = 0; kx < 3; ++kx) {
-                const bf16x8 bv = tr_fragment(X[ky], 8 * g + kx, nt, lane);
-                const bf16x8 a = kx == 0 ? a0 : (kx == 1 ? a1 : a2);
-                acc[ky * 3 + kx] = mfma(a, bv, acc[ky * 3 + kx]);
+            for (int ky = 0; ky < 3; ++ky) {
+#pragma unroll
+                for (int kx = 0; kx < 3; ++kx) {
+                    const bf16x8 bv = tr_fragment(X[ky], pb + kx, nt, lane);
+                    const bf16x8 a = kx == 0 ? a0 : (kx == 1 ? a1 : a2);
+                    acc[ky * 3 + kx] = mfma(a, bv, acc[ky * 3 + kx]);
+                }
             }
         }
         if (do_bias && t < 32) {
 #pragma unroll 8
-            for (int j = 0; j < 32; ++j) bsum += (float)Z[j * kWP + t];
+            for (int j = 0; j < CH; ++j) bsum += (float)Z[j * kWP + t];
         }
     }
     // partial tile of this block
@@ -747,7 +760,7 @@ int fwi_nn_wgrad(const void *x, const void *dz, float *dw, float *db, int32_t N,
     hipStream_t st = static_cast<hipStream_t>(stream);
     float *part = static_cast<float *>(ws);
     float *bpart = part + (size_t)nsplit * Co * 9 * Ci;
-    hipLaunchKernelGGL(k_wgrad, dim3(nsplit, (Co / 32) * (Ci / 32)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_wgrad<kWgradChunk>, dim3(nsplit, (Co / 32) * (Ci / 32)), dim3(256), 0, st,
                        static_cast<const bf16 *>(x), static_cast<const bf16 *>(dz), part, bpart, N,
                        H, W, Ci, Co);
     hipError_t e = hipGetLastError();

@@ -281,6 +281,7 @@ class Net:
 
     WGRAD_BLOCKS = 1024
     WGRAD_MAX_SPLIT = 512
+    WGRAD_CHUNK = 64
 
     def __init__(self, params: np.ndarray | torch.Tensor | None = None, seed: int = 0,
                  device="cuda", out_scale: float = 0.0):
@@ -349,12 +350,13 @@ class Net:
         self.g2 = torch.empty(maxn, dtype=BF, device=dev)
         self.g3 = torch.empty(maxn, dtype=BF, device=dev)
         self.gskip = {0: act(0, 32), 1: act(1, 64), 2: act(2, 128)}
-        # weight-gradient split: enough blocks to fill the chip, at most one chunk each
+        # weight-gradient split: enough blocks to fill the chip, at most one
+        # chunk (WGRAD_CHUNK pixels, the kernel's staging step) each
         self.nsplit = []
         wsb = 0
         for _, ci, co, lv, _ in LAYERS:
             h, w = hw[lv]
-            chunks = (N * h * w + 31) // 32
+            chunks = (N * h * w + self.WGRAD_CHUNK - 1) // self.WGRAD_CHUNK
             tiles = (co // 32) * (ci // 32)
             ns = int(max(1, min(chunks, (self.WGRAD_BLOCKS + tiles - 1) // tiles,
                                 self.WGRAD_MAX_SPLIT)))
@@ -476,11 +478,66 @@ def conv_flops(N: int, H: int, W: int, training: bool) -> float:
     return tot
 
 
+HBM_PEAK_BPS = 8.0e12          # MI355X HBM3E, AMD public specification
+BF16_PEAK_FLOPS = 2.5e15       # MI355X dense BF16 MFMA, AMD public specification
+
+
+def layer_report(net: "Net", N: int, H: int, W: int, reps: int = 20) -> list:
+    """Per layer of a training step: the average time of its forward
+    convolution, its input-gradient convolution (flipped weights) and its
+    weight gradient, each against its own roofline bound max(flops / BF16
+    peak, bytes / HBM peak).  Bytes count the activations read and written
+    once (bf16) and the weights; flops are 2 * 9 * Ci * Co per pixel."""
+    hw = [(H >> lv, W >> lv) for lv in range(4)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    rows = []
+    for k, (name, ci, co, lv, relu) in enumerate(LAYERS):
+        h, w = hw[lv]
+        npx = N * h * w
+        x = torch.zeros(npx * ci, dtype=BF, device=net.device)
+        y = torch.zeros(npx * co, dtype=BF, device=net.device)
+        wf = torch.empty(co * 9 * ci, dtype=BF, device=net.device)
+        flip(net.w(k), wf, ci, co)
+        flops = 2.0 * 9 * ci * co * npx
+        act_bytes = 2.0 * npx * (ci + co)
+        kinds = {
+            "fwd": (lambda: conv3x3(x, net.w(k), net.b(k), y, N, h, w, ci, co, relu),
+                    act_bytes + 2.0 * 9 * ci * co),
+            "dgrad": (lambda: conv3x3(y, wf, None, x, N, h, w, co, ci, False),
+                      act_bytes + 2.0 * 9 * ci * co),
+            "wgrad": (lambda: wgrad(x, y, net.gw(k), net.gb(k), N, h, w, ci, co, net.nsplit[k],
+                                    net.wsg),
+                      act_bytes + 4.0 * 9 * ci * co),
+        }
+        rec = {"layer": name, "Ci": ci, "Co": co, "image": [h, w], "GFLOP": round(flops / 1e9, 3)}
+        for kind, (fn, nbytes) in kinds.items():
+            t = timed(fn)
+            bound = max(flops / BF16_PEAK_FLOPS, nbytes / HBM_PEAK_BPS)
+            rec[kind] = {"us": round(t * 1e6, 2), "TFLOPs": round(flops / t / 1e12, 1),
+                         "bound": "mfma" if flops / BF16_PEAK_FLOPS >= nbytes / HBM_PEAK_BPS
+                         else "hbm", "frac_of_bound": round(bound / t, 4)}
+        rows.append(rec)
+    return rows
+
+
 def main(argv=None):
     import argparse
     import json
     import sys
     ap = argparse.ArgumentParser(description="throughput of the preconditioner network kernels")
+    ap.add_argument("--layers", action="store_true",
+                    help="also time every layer's three convolution kernels against their bounds")
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--size", default="128x128", help="training image HxW")
     ap.add_argument("--steps", type=int, default=40)
@@ -535,6 +592,9 @@ def main(argv=None):
     out["infer"] = {"image": [Hi, Wi], "ms": round(ms, 4),
                     "TFLOPs": round(conv_flops(1, Hi, Wi, False) / ms * 1e-9, 2)}
     out["peak_bf16_TFLOPs"] = 2500.0
+    if args.layers:
+        net._buffers(N, H, W)
+        out["layers"] = layer_report(net, N, H, W)
     print(json.dumps(out), flush=True)
     return 0
 
