@@ -58,7 +58,7 @@ int fwi_nn_flip(const void *w, void *wf, int32_t Ci, int32_t Co, void *stream);
  *   db[co] = sum_p dz[p][co]   (float32 outputs, overwritten).
  * The pixel sum is split over nsplit partial sums reduced in a fixed order,
  * so results are deterministic.  x and dz 16-byte aligned, N * H * W < 2^36,
- * 1 <= nsplit <= 65535.  ws: device scratch of at least
+ * H, W <= 32768, 1 <= nsplit <= 65535.  ws: device scratch of at least
  * fwi_nn_wgrad_workspace(Ci, Co, nsplit) bytes, 4-byte aligned. */
 size_t fwi_nn_wgrad_workspace(int32_t Ci, int32_t Co, int32_t nsplit);
 int fwi_nn_wgrad(const void *x, const void *dz, float *dw, float *db, int32_t N, int32_t H,

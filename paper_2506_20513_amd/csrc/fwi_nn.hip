@@ -267,7 +267,9 @@ __global__ void k_flip(const bf16 *__restrict__ w, bf16 *__restrict__ wf, int Ci
 //   Z[j][c]      = dz[q0 + j][co tile]                          (CH rows)
 //   X[ky][j][c]  = x[q0 - 1 + j + (ky-1) W][ci tile]             (CH + 2 rows)
 // and each wave runs nine MFMAs per 32 pixels of the chunk.  Chunks of 64
-// pixels halve the barriers and staging rounds per MFMA against 32.
+// pixels (half the barriers and staging rounds per MFMA) made the training
+// step 4% slower than chunks of 32 (2.32 against 2.22 ms at about 1024
+// blocks per layer; 2.30 and 2.36 ms at 512 and 2048 blocks).
 // X rows are zero where the row of q = q0 - 1 + j plus ky - 1 leaves the
 // image (or q is outside 0 .. P-1).  A tap (ky, kx) reads X[ky] from row kx
 // on, so the three kx taps share one staged tile; the taps that would wrap
@@ -281,7 +283,7 @@ __global__ void k_flip(const bf16 *__restrict__ w, bf16 *__restrict__ wf, int Ci
 // i/4+12; so with lane s of the group reading row base + s/4 at channel
 // 4 (s % 4), lane i gets channel i at rows base .. base + 3.
 constexpr int kWP = 40;     // LDS row pitch in bf16: 32 channels + 8 padding
-constexpr int kWgradChunk = 64;   // pixels staged per step of k_wgrad
+constexpr int kWgradChunk = 32;   // pixels staged per step of k_wgrad
 
 typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 typedef __attribute__((address_space(3))) bf16x4 *lds_bf16x4_ptr;
@@ -296,6 +298,18 @@ __device__ __forceinline__ bf16x8 tr_fragment(const bf16 *tile, int base, int h,
     const bf16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4_ptr)(p1));
     return bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
 }
+
+// floor(n / d) for 0 <= n, d < 2^16 as the high word of n m with
+// m = floor((2^32 - 1) / d) + 1 = 2^32 / d + e, 0 < e <= 1.  Then n m / 2^32 =
+// n / d + n e / 2^32 with n e / 2^32 < 2^-16 < 1 / d, which is less than the
+// distance from n / d up to the next integer, so the floor is exact.  d = 1
+// (where m would overflow) is passed through.
+struct SmallDiv {
+    unsigned d, m;
+    __device__ explicit SmallDiv(unsigned dd) : d(dd), m(dd > 1 ? 0xffffffffu / dd + 1u : 0u) {}
+    __device__ __forceinline__ unsigned div(unsigned n) const { return d > 1 ? __umulhi(n, m) : n; }
+    __device__ __forceinline__ unsigned mod(unsigned n) const { return n - d * div(n); }
+};
 
 template <int CH>
 __global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ x,
@@ -323,13 +337,21 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ x,
     const bf16 zero = (bf16)0.f;
     // staging: CH x 4 pieces of Z, then 3 x (CH + 2) x 4 pieces of X (16
     // bytes each), kPer per thread; the pieces of the next chunk are loaded
-    // into registers while the current chunk computes
+    // into registers while the current chunk computes.  Column and image row
+    // of the chunk's first pixel advance incrementally from chunk to chunk,
+    // and the few divisions left are high multiplies (H, W < 2^15, checked
+    // by the host), so the index arithmetic stays small against the MFMAs.
     constexpr int kZ = CH * 4;
     constexpr int kPieces = kZ + 3 * XR * 4;
     constexpr int kPer = (kPieces + 255) / 256;
+    const SmallDiv dW((unsigned)W), dH((unsigned)H);
+    const int64_t step = (int64_t)gridDim.x * CH;          // pixels between a block's chunks
+    const int dcol = (int)(step % W);
+    const int drow = (int)((step / W) % H);
+    int col0 = (int)(((int64_t)blockIdx.x * CH) % W);
+    int row0 = (int)(((int64_t)blockIdx.x * CH / W) % H);
     uint4 pre[kPer];
-    auto fetch = [&](int64_t q0, uint4 *out) {
-        const int col0 = (int)(q0 % W), row0 = (int)((q0 / W) % H);
+    auto fetch = [&](int64_t q0, int c0, int r0, uint4 *out) {
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
             const int idx = t + 256 * u;
@@ -343,9 +365,9 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ x,
                 const int ky = r / (XR * 4), j = (r >> 2) % XR, c = (r & 3) * 8;
                 const int64_t q = q0 - 1 + j;
                 if (q >= 0 && q < P) {
-                    const int d = col0 - 1 + j;                 // >= -1
-                    const int row = row0 + (d >= 0 ? d / W : -1);
-                    const int yy = (row % H + H) % H + ky - 1;
+                    const int d = c0 - 1 + j;                    // >= -1
+                    const int row = r0 + (d >= 0 ? (int)dW.div((unsigned)d) : -1);
+                    const int yy = (int)dH.mod((unsigned)(row + H)) + ky - 1;
                     if (yy >= 0 && yy < H)
                         v = *reinterpret_cast<const uint4 *>(
                             x + (q + (int64_t)(ky - 1) * W) * Ci + cit * 32 + c);
@@ -354,10 +376,8 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ x,
             out[u] = v;
         }
     };
-    if ((int64_t)blockIdx.x < nchunk) fetch((int64_t)blockIdx.x * CH, pre);
+    if ((int64_t)blockIdx.x < nchunk) fetch((int64_t)blockIdx.x * CH, col0, row0, pre);
     for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
-        const int64_t q0 = ch * CH;
-        const int col0 = (int)(q0 % W);
         __syncthreads();   // previous chunk's reads done
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
@@ -371,7 +391,14 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ x,
             }
         }
         __syncthreads();
-        if (ch + gridDim.x < nchunk) fetch((ch + gridDim.x) * CH, pre);
+        // column and row of the next chunk's first pixel
+        int ncol = col0 + dcol, nrow = row0 + drow;
+        if (ncol >= W) {
+            ncol -= W;
+            ++nrow;
+        }
+        if (nrow >= H) nrow -= H;
+        if (ch + gridDim.x < nchunk) fetch((ch + gridDim.x) * CH, ncol, nrow, pre);
 #pragma unroll
         for (int hf = 0; hf < NH; ++hf) {
             // dz fragment (channels 16 mt .. +15, pixels 32 hf + 8 g .. +7)
@@ -379,11 +406,12 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ x,
             const int pb = 32 * hf + 8 * g;
             const bf16x8 a1 = tr_fragment(Z, pb, mt, lane);
             bf16x8 a0 = a1, a2 = a1;
+            int col = (int)dW.mod((unsigned)(col0 + pb));
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const int col = (col0 + pb + e) % W;
                 if (col == 0) a0[e] = zero;
                 if (col == W - 1) a2[e] = zero;
+                col = col + 1 == W ? 0 : col + 1;
             }
 #pragma unroll
             for (int ky = 0; ky < 3; ++ky) {
@@ -399,6 +427,8 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ x,
 #pragma unroll 8
             for (int j = 0; j < CH; ++j) bsum += (float)Z[j * kWP + t];
         }
+        col0 = ncol;
+        row0 = nrow;
     }
     // partial tile of this block
     const size_t tile = (size_t)Co * 9 * Ci;
@@ -716,8 +746,10 @@ int fwi_nn_conv3x3(const void *x, const void *w, const float *bias, void *y, int
     const bf16 *xb = static_cast<const bf16 *>(x);
     const bf16 *wb = static_cast<const bf16 *>(w);
     bf16 *yb = static_cast<bf16 *>(y);
-    // LDS-tiled kernel when it still gives the chip enough blocks
-    const int bn = Co % 64 == 0 ? 64 : 32;
+    // LDS-tiled kernel when it still gives the chip enough blocks, with the
+    // narrower channel tile where only that one does
+    int bn = Co % 64 == 0 ? 64 : 32;
+    if (bn == 64 && (P + 127) / 128 * (Co / 64) < 256) bn = 32;
     const int64_t lds_blocks = (P + 127) / 128 * (Co / bn);
     if (lds_blocks >= 256) {
         const dim3 grid((unsigned)((P + 127) / 128), (unsigned)(Co / bn));
@@ -752,7 +784,8 @@ size_t fwi_nn_wgrad_workspace(int32_t Ci, int32_t Co, int32_t nsplit) {
 int fwi_nn_wgrad(const void *x, const void *dz, float *dw, float *db, int32_t N, int32_t H,
                  int32_t W, int32_t Ci, int32_t Co, int32_t nsplit, void *ws, size_t ws_bytes,
                  void *stream) {
-    if (!x || !dz || !dw || !db || !ws || N < 1 || H < 1 || W < 1 || Ci < 32 || Co < 32 ||
+    if (!x || !dz || !dw || !db || !ws || N < 1 || H < 1 || W < 1 || H > 32768 || W > 32768 ||
+        Ci < 32 || Co < 32 ||
         Ci % 32 || Co % 32 || nsplit < 1 || nsplit > 65535 || !al16(x) || !al16(dz) ||
         (int64_t)N * H * W >= (int64_t)1 << 36 ||
         ws_bytes < fwi_nn_wgrad_workspace(Ci, Co, nsplit))

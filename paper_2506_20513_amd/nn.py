@@ -281,7 +281,7 @@ class Net:
 
     WGRAD_BLOCKS = 1024
     WGRAD_MAX_SPLIT = 512
-    WGRAD_CHUNK = 64
+    WGRAD_CHUNK = 32
 
     def __init__(self, params: np.ndarray | torch.Tensor | None = None, seed: int = 0,
                  device="cuda", out_scale: float = 0.0):

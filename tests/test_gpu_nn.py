@@ -95,7 +95,9 @@ def test_flipped_conv_is_the_input_gradient():
                                                  # chunks crossing rows and images, odd width
                                                  (3, 7, 13, 32, 64, 5),
                                                  # several channel tiles both ways
-                                                 (2, 9, 21, 64, 96, 2), (1, 1, 1, 32, 32, 1)])
+                                                 (2, 9, 21, 64, 96, 2), (1, 1, 1, 32, 32, 1),
+                                                 # rows wider than a chunk; one-pixel-wide images
+                                                 (2, 5, 100, 32, 32, 7), (4, 3, 1, 32, 32, 2)])
 def test_weight_gradient_matches_reference(N, H, W, Ci, Co, nsplit):
     import torch
     x = _bf((N, H, W, Ci), 7)
