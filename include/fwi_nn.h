@@ -43,7 +43,8 @@ extern "C" {
 
 /* y = act(conv3x3(x, w) + bias), act = ReLU if relu != 0 else identity.
  * x [N][H][W][Ci], y [N][H][W][Co] bf16 (must not alias x); w [Co][3][3][Ci]
- * bf16; bias [Co] float32 or NULL.  Ci, Co multiples of 32; N * H * W < 2^36.
+ * bf16; bias [Co] float32 or NULL.  Ci, Co multiples of 32; N * H * W < 2^36;
+ * H, W <= 32768.
  * The input gradient of a convolution is fwi_nn_conv3x3 applied to the
  * output gradient with the weights from fwi_nn_flip (Ci and Co swapped). */
 int fwi_nn_conv3x3(const void *x, const void *w, const float *bias, void *y, int32_t N,

@@ -25,6 +25,19 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
 }
 
 // ---------------------------------------------------------------------------
+// floor(n / d) for n d < 2^32 as the high word of n m with
+// m = floor((2^32 - 1) / d) + 1 = 2^32 / d + e, 0 < e <= 1.  Then n m / 2^32 =
+// n / d + n e / 2^32 with n e / 2^32 <= n / 2^32 < 1 / d, less than the
+// distance from n / d up to the next integer, so the floor is exact.  d = 1
+// (where m would overflow) is passed through.  The convolution kernels use
+// it with d = H or W <= 2^15 (checked by the host) and n < 2 d + 2^8.
+struct SmallDiv {
+    unsigned d, m;
+    __device__ explicit SmallDiv(unsigned dd) : d(dd), m(dd > 1 ? 0xffffffffu / dd + 1u : 0u) {}
+    __device__ __forceinline__ unsigned div(unsigned n) const { return d > 1 ? __umulhi(n, m) : n; }
+    __device__ __forceinline__ unsigned mod(unsigned n) const { return n - d * div(n); }
+};
+
 // y = act(conv3x3(x, w) + bias) as an implicit GEMM: rows are output pixels
 // in flattened (n, y, x) order, columns output channels, the reduction runs
 // over (ky, kx, ci).  Tiling over flattened pixels keeps every lane busy on
@@ -111,25 +124,28 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ x,
 }
 
 // The same convolution with both operand tiles staged in LDS: a block
-// computes 128 consecutive (flattened) pixels x BN output channels.  A
-// reduction step covers one kernel row ky and 32 input channels for all
-// three kx taps: it stages the input rows of pixels base - 1 .. base + 128
-// shifted by ky - 1 image rows (130 rows, zero where that row leaves the
-// image) and the three BN x 32 weight tiles of (ky, kx = 0, 1, 2).  Tap kx
-// of output pixel p reads staged row p - base + kx, so the three taps share
-// the staged rows; a tap that would wrap across a row edge (kx = 0 at column
-// 0, kx = 2 at column W-1) gets a zero fragment.  Two LDS buffers, one
+// computes BM (128 or 64) consecutive (flattened) pixels x BN output
+// channels.  A reduction step covers one kernel row ky and 32 input channels
+// for all three kx taps: it stages the input rows of pixels base - 1 ..
+// base + BM shifted by ky - 1 image rows (BM + 2 rows, zero where that row
+// leaves the image) and the three BN x 32 weight tiles of (ky, kx = 0, 1, 2).
+// Tap kx of output pixel p reads staged row p - base + kx, so the three taps
+// share the staged rows; a tap that would wrap across a row edge (kx = 0 at
+// column 0, kx = 2 at column W-1) gets a zero fragment.  Two LDS buffers, one
 // barrier per step; the global loads of step k+1 are in flight while step k
-// issues its 3 x 2 x BN/16 MFMAs per wave.
+// issues its 3 x (BM / 64) x BN/16 MFMAs per wave.  The 64-pixel tile
+// doubles the blocks of layers with few pixels, where one block per CU
+// leaves every global-load latency exposed.
 constexpr int kTP = 40;      // LDS row pitch in bf16: 32 channels + 8 padding (80 bytes)
 
-template <int BN>
+template <int BN, int BM>
 __global__ __launch_bounds__(256) void k_conv3x3_lds(const bf16 *__restrict__ x,
                                                      const bf16 *__restrict__ w,
                                                      const float *__restrict__ bias,
                                                      bf16 *__restrict__ y, int N, int H, int W,
                                                      int Ci, int Co, int relu) {
-    constexpr int BM = 128, AR = BM + 2, NTL = BN / 16;
+    static_assert(BM == 64 || BM == 128, "64 or 128 pixels per block");
+    constexpr int AR = BM + 2, NTL = BN / 16, MW = BM / 64;   // MW: 16-pixel tiles per wave
     constexpr int APieces = AR * 4, BPieces = 3 * BN * 4;     // 16-byte pieces per step
     constexpr int AU = (APieces + 255) / 256, BU = (BPieces + 255) / 256;
     __shared__ __attribute__((aligned(16))) bf16 As[2][AR * kTP];
@@ -140,12 +156,13 @@ __global__ __launch_bounds__(256) void k_conv3x3_lds(const bf16 *__restrict__ x,
     const int co0 = blockIdx.y * BN;
     const int col0 = (int)(base % W), row0 = (int)((base / W) % H);
     const int nck = Ci / 32, K = 3 * nck;
+    const SmallDiv dW((unsigned)W), dH((unsigned)H);
     // this lane's output pixels (offsets in the block) and their columns
-    int pofs[2], pcol[2];
+    int pofs[MW], pcol[MW];
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
-        pofs[m] = wave * 32 + m * 16 + (lane & 15);
-        pcol[m] = (col0 + pofs[m]) % W;
+    for (int m = 0; m < MW; ++m) {
+        pofs[m] = wave * 16 * MW + m * 16 + (lane & 15);
+        pcol[m] = (int)dW.mod((unsigned)(col0 + pofs[m]));
     }
     uint4 ra[AU], rb[BU];
     auto fetch = [&](int k) {
@@ -159,8 +176,8 @@ __global__ __launch_bounds__(256) void k_conv3x3_lds(const bf16 *__restrict__ x,
                 const int64_t q = base - 1 + j;
                 if (q >= 0 && q < P) {
                     const int d = col0 - 1 + j;                 // >= -1
-                    const int row = row0 + (d >= 0 ? d / W : -1);
-                    const int yy = (row % H + H) % H + ky - 1;
+                    const int row = row0 + (d >= 0 ? (int)dW.div((unsigned)d) : -1);
+                    const int yy = (int)dH.mod((unsigned)(row + H)) + ky - 1;
                     if (yy >= 0 && yy < H)
                         v = *reinterpret_cast<const uint4 *>(
                             x + (q + (int64_t)(ky - 1) * W) * Ci + c0 + c);
@@ -195,9 +212,9 @@ __global__ __launch_bounds__(256) void k_conv3x3_lds(const bf16 *__restrict__ x,
                 *reinterpret_cast<uint4 *>(&Bs[buf][(idx >> 2) * kTP + (idx & 3) * 8]) = rb[u];
         }
     };
-    f32x4 acc[2][NTL];
+    f32x4 acc[MW][NTL];
 #pragma unroll
-    for (int m = 0; m < 2; ++m)
+    for (int m = 0; m < MW; ++m)
 #pragma unroll
         for (int n = 0; n < NTL; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bf16x8 zero{};
@@ -209,9 +226,9 @@ __global__ __launch_bounds__(256) void k_conv3x3_lds(const bf16 *__restrict__ x,
         if (k + 1 < K) fetch(k + 1);
 #pragma unroll
         for (int kx = 0; kx < 3; ++kx) {
-            bf16x8 a[2];
+            bf16x8 a[MW];
 #pragma unroll
-            for (int m = 0; m < 2; ++m) {
+            for (int m = 0; m < MW; ++m) {
                 a[m] = *reinterpret_cast<const bf16x8 *>(
                     &As[buf][(pofs[m] + kx) * kTP + 8 * (lane >> 4)]);
                 if ((kx == 0 && pcol[m] == 0) || (kx == 2 && pcol[m] == W - 1)) a[m] = zero;
@@ -221,7 +238,7 @@ __global__ __launch_bounds__(256) void k_conv3x3_lds(const bf16 *__restrict__ x,
                 const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(
                     &Bs[buf][(kx * BN + n * 16 + (lane & 15)) * kTP + 8 * (lane >> 4)]);
 #pragma unroll
-                for (int m = 0; m < 2; ++m) acc[m][n] = mfma(a[m], bv, acc[m][n]);
+                for (int m = 0; m < MW; ++m) acc[m][n] = mfma(a[m], bv, acc[m][n]);
             }
         }
         if (k + 1 < K) stash(buf ^ 1);
@@ -232,10 +249,10 @@ __global__ __launch_bounds__(256) void k_conv3x3_lds(const bf16 *__restrict__ x,
         const int co = co0 + n * 16 + (lane & 15);
         const float bb = bias ? bias[co] : 0.f;
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
+        for (int m = 0; m < MW; ++m) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t po = base + wave * 32 + m * 16 + 4 * (lane >> 4) + r;
+                const int64_t po = base + wave * 16 * MW + m * 16 + 4 * (lane >> 4) + r;
                 if (po < P) {
                     float v = acc[m][n][r] + bb;
                     if (relu) v = fmaxf(v, 0.f);
@@ -261,7 +278,7 @@ __global__ void k_flip(const bf16 *__restrict__ w, bf16 *__restrict__ wf, int Ci
 // db[co] = sum_q dz[q][co].  A GEMM whose reduction runs over output pixels
 // q: a block owns a 32 (co) x 32 (ci) tile for all nine taps, loops over
 // every gridDim.x-th chunk of CH pixels and writes its partial sums to
-// part[blockIdx.x].
+// record blockIdx.x of part (Co 9 Ci weight sums, then Co bias sums).
 //
 // Per chunk q0 .. q0+CH-1 the block stages, in natural (pixel-major) layout:
 //   Z[j][c]      = dz[q0 + j][co tile]                          (CH rows)
@@ -299,23 +316,10 @@ __device__ __forceinline__ bf16x8 tr_fragment(const bf16 *tile, int base, int h,
     return bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
 }
 
-// floor(n / d) for 0 <= n, d < 2^16 as the high word of n m with
-// m = floor((2^32 - 1) / d) + 1 = 2^32 / d + e, 0 < e <= 1.  Then n m / 2^32 =
-// n / d + n e / 2^32 with n e / 2^32 < 2^-16 < 1 / d, which is less than the
-// distance from n / d up to the next integer, so the floor is exact.  d = 1
-// (where m would overflow) is passed through.
-struct SmallDiv {
-    unsigned d, m;
-    __device__ explicit SmallDiv(unsigned dd) : d(dd), m(dd > 1 ? 0xffffffffu / dd + 1u : 0u) {}
-    __device__ __forceinline__ unsigned div(unsigned n) const { return d > 1 ? __umulhi(n, m) : n; }
-    __device__ __forceinline__ unsigned mod(unsigned n) const { return n - d * div(n); }
-};
-
 template <int CH>
 __global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ x,
                                                const bf16 *__restrict__ dz,
-                                               float *__restrict__ part,
-                                               float *__restrict__ bpart, int N, int H, int W,
+                                               float *__restrict__ part, int N, int H, int W,
                                                int Ci, int Co) {
     static_assert(CH % 32 == 0, "chunks of whole 32-pixel fragments");
     constexpr int NH = CH / 32;                   // 32-pixel halves per chunk
@@ -339,8 +343,8 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ x,
     // bytes each), kPer per thread; the pieces of the next chunk are loaded
     // into registers while the current chunk computes.  Column and image row
     // of the chunk's first pixel advance incrementally from chunk to chunk,
-    // and the few divisions left are high multiplies (H, W < 2^15, checked
-    // by the host), so the index arithmetic stays small against the MFMAs.
+    // and the few divisions left are high multiplies, so the index
+    // arithmetic stays small against the MFMAs.
     constexpr int kZ = CH * 4;
     constexpr int kPieces = kZ + 3 * XR * 4;
     constexpr int kPer = (kPieces + 255) / 256;
@@ -430,9 +434,10 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ x,
         col0 = ncol;
         row0 = nrow;
     }
-    // partial tile of this block
+    // this block's partial sums: record blockIdx.x of Co 9 Ci weight sums
+    // followed by Co bias sums
     const size_t tile = (size_t)Co * 9 * Ci;
-    float *o = part + blockIdx.x * tile;
+    float *o = part + blockIdx.x * (tile + Co);
 #pragma unroll
     for (int k = 0; k < 9; ++k)
 #pragma unroll
@@ -441,29 +446,45 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ x,
             const int ci = cit * 32 + 16 * nt + (lane & 15);
             o[((size_t)co * 9 + k) * Ci + ci] = acc[k][r];
         }
-    if (do_bias && t < 32) bpart[(size_t)blockIdx.x * Co + cot * 32 + t] = bsum;
+    if (do_bias && t < 32) o[tile + cot * 32 + t] = bsum;
 }
 
-// out[i] = sum_k part[k][i]: 64 outputs per block, four groups of waves
-// summing the splits k = g (mod 4) with four accumulators each, combined in
-// a fixed order (deterministic).
-__global__ __launch_bounds__(256) void k_reduce(const float *__restrict__ part,
-                                                float *__restrict__ out, size_t n, int nsplit) {
-    __shared__ float red[4][64];
+// sum_k part[k][i] over the nsplit records of n = n1 + n2 floats, written
+// to out1[i] for i < n1 and to out2[i - n1] after: 64 outputs per block, GR
+// groups of waves summing the splits k = g (mod GR) with four loads in
+// flight each, combined in a fixed order (deterministic).  GR = 16 gives
+// small layers (few outputs, many splits) more loads in flight per output.
+template <int GR>
+__global__ __launch_bounds__(64 * GR) void k_reduce(const float *__restrict__ part,
+                                                    float *__restrict__ out1,
+                                                    float *__restrict__ out2, size_t n1, size_t n,
+                                                    int nsplit) {
+    __shared__ float red[GR][64];
     const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
     const size_t i = (size_t)blockIdx.x * 64 + lane;
-    float s[4] = {0.f, 0.f, 0.f, 0.f};
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
     if (i < n) {
         int k = g;
-        for (; k + 12 < nsplit; k += 16) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) s[u] += part[(size_t)(k + 4 * u) * n + i];
+        for (; k + 3 * GR < nsplit; k += 4 * GR) {
+            s0 += part[(size_t)k * n + i];
+            s1 += part[(size_t)(k + GR) * n + i];
+            s2 += part[(size_t)(k + 2 * GR) * n + i];
+            s3 += part[(size_t)(k + 3 * GR) * n + i];
         }
-        for (int u = 0; k < nsplit; k += 4, ++u) s[u] += part[(size_t)k * n + i];
+        if (k < nsplit) s0 += part[(size_t)k * n + i];
+        if (k + GR < nsplit) s1 += part[(size_t)(k + GR) * n + i];
+        if (k + 2 * GR < nsplit) s2 += part[(size_t)(k + 2 * GR) * n + i];
     }
-    red[g][lane] = (s[0] + s[1]) + (s[2] + s[3]);
+    red[g][lane] = (s0 + s1) + (s2 + s3);
     __syncthreads();
-    if (g == 0 && i < n) out[i] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+    if (g != 0 || i >= n) return;
+    float tot = red[0][lane];
+#pragma unroll
+    for (int v = 1; v < GR; ++v) tot += red[v][lane];
+    if (i < n1)
+        out1[i] = tot;
+    else
+        out2[i - n1] = tot;
 }
 
 // ---------------------------------------------------------------------------
@@ -737,8 +758,8 @@ extern "C" {
 
 int fwi_nn_conv3x3(const void *x, const void *w, const float *bias, void *y, int32_t N,
                    int32_t H, int32_t W, int32_t Ci, int32_t Co, int32_t relu, void *stream) {
-    if (!x || !w || !y || N < 1 || H < 1 || W < 1 || Ci < 32 || Co < 32 || Ci % 32 || Co % 32 ||
-        !al16(x) || !al16(w))
+    if (!x || !w || !y || N < 1 || H < 1 || W < 1 || H > 32768 || W > 32768 || Ci < 32 ||
+        Co < 32 || Ci % 32 || Co % 32 || !al16(x) || !al16(w))
         return FWI_NN_EINVAL;
     if ((int64_t)N * H * W >= (int64_t)1 << 36) return FWI_NN_EINVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -747,18 +768,28 @@ int fwi_nn_conv3x3(const void *x, const void *w, const float *bias, void *y, int
     const bf16 *wb = static_cast<const bf16 *>(w);
     bf16 *yb = static_cast<bf16 *>(y);
     // LDS-tiled kernel when it still gives the chip enough blocks, with the
-    // narrower channel tile where only that one does
+    // narrower channel tile where only that one does, and 64-pixel blocks
+    // where 128-pixel blocks would leave fewer than two blocks per CU
     int bn = Co % 64 == 0 ? 64 : 32;
     if (bn == 64 && (P + 127) / 128 * (Co / 64) < 256) bn = 32;
     const int64_t lds_blocks = (P + 127) / 128 * (Co / bn);
     if (lds_blocks >= 256) {
-        const dim3 grid((unsigned)((P + 127) / 128), (unsigned)(Co / bn));
-        if (bn == 64)
-            hipLaunchKernelGGL(k_conv3x3_lds<64>, grid, dim3(256), 0, st, xb, wb, bias, yb, N, H,
-                               W, Ci, Co, relu);
+        // (the 64-pixel tile below 1024 blocks of 128 made the network's
+        // 32 x 32-pixel layers slower)
+        const int bm = lds_blocks < 512 ? 64 : 128;
+        const dim3 grid((unsigned)((P + bm - 1) / bm), (unsigned)(Co / bn));
+        if (bn == 64 && bm == 128)
+            hipLaunchKernelGGL((k_conv3x3_lds<64, 128>), grid, dim3(256), 0, st, xb, wb, bias, yb,
+                               N, H, W, Ci, Co, relu);
+        else if (bn == 64)
+            hipLaunchKernelGGL((k_conv3x3_lds<64, 64>), grid, dim3(256), 0, st, xb, wb, bias, yb,
+                               N, H, W, Ci, Co, relu);
+        else if (bm == 128)
+            hipLaunchKernelGGL((k_conv3x3_lds<32, 128>), grid, dim3(256), 0, st, xb, wb, bias, yb,
+                               N, H, W, Ci, Co, relu);
         else
-            hipLaunchKernelGGL(k_conv3x3_lds<32>, grid, dim3(256), 0, st, xb, wb, bias, yb, N, H,
-                               W, Ci, Co, relu);
+            hipLaunchKernelGGL((k_conv3x3_lds<32, 64>), grid, dim3(256), 0, st, xb, wb, bias, yb,
+                               N, H, W, Ci, Co, relu);
         return status(hipGetLastError());
     }
     // small layers: 64-pixel blocks of 32-channel tiles (four times the
@@ -792,18 +823,18 @@ int fwi_nn_wgrad(const void *x, const void *dz, float *dw, float *db, int32_t N,
         return FWI_NN_EINVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
     float *part = static_cast<float *>(ws);
-    float *bpart = part + (size_t)nsplit * Co * 9 * Ci;
     hipLaunchKernelGGL(k_wgrad<kWgradChunk>, dim3(nsplit, (Co / 32) * (Ci / 32)), dim3(256), 0, st,
-                       static_cast<const bf16 *>(x), static_cast<const bf16 *>(dz), part, bpart, N,
-                       H, W, Ci, Co);
+                       static_cast<const bf16 *>(x), static_cast<const bf16 *>(dz), part, N, H, W,
+                       Ci, Co);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return FWI_NN_EHIP;
-    const size_t nw = (size_t)Co * 9 * Ci;
-    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((nw + 63) / 64)), dim3(256), 0, st, part, dw, nw,
-                       nsplit);
-    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((Co + 63) / 64)), dim3(256), 0, st, bpart, db,
-                       (size_t)Co,
-                       nsplit);
+    const size_t nw = (size_t)Co * 9 * Ci, n = nw + Co;
+    const unsigned nb = (unsigned)((n + 63) / 64);
+    // sixteen wave groups where the outputs give fewer than 1024 blocks
+    if (nb < 1024)
+        hipLaunchKernelGGL(k_reduce<16>, dim3(nb), dim3(1024), 0, st, part, dw, db, nw, n, nsplit);
+    else
+        hipLaunchKernelGGL(k_reduce<4>, dim3(nb), dim3(256), 0, st, part, dw, db, nw, n, nsplit);
     return status(hipGetLastError());
 }
 

@@ -280,7 +280,7 @@ class Net:
     reduction to read)."""
 
     WGRAD_BLOCKS = 1024
-    WGRAD_MAX_SPLIT = 512
+    WGRAD_MAX_SPLIT = 1024
     WGRAD_CHUNK = 32
 
     def __init__(self, params: np.ndarray | torch.Tensor | None = None, seed: int = 0,

@@ -248,6 +248,10 @@ def test_nn_argument_checks():
     assert L.fwi_nn_conv3x3(A, A, None, A, 0, 8, 8, 32, 32, 1, None) == E
     assert L.fwi_nn_conv3x3(A, A, None, A, 1 << 16, 1 << 15, 1 << 5, 32, 32, 1, None) == E
     assert L.fwi_nn_wgrad(A + 8, A, A, A, 1, 8, 8, 32, 64, 4, A, 1 << 30, None) == E
+    # image sides above 2^15 (the kernels' exact division range)
+    assert L.fwi_nn_conv3x3(A, A, None, A, 1, 32769, 1, 32, 32, 1, None) == E
+    assert L.fwi_nn_conv3x3(A, A, None, A, 1, 1, 32769, 32, 32, 1, None) == E
+    assert L.fwi_nn_wgrad(A, A, A, A, 1, 1, 32769, 32, 64, 4, A, 1 << 30, None) == E
     # weight gradient: workspace size and split count
     need = L.fwi_nn_wgrad_workspace(32, 64, 4)
     assert need == (4 * 64 * 9 * 32 + 4 * 64) * 4

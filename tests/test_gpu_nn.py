@@ -57,10 +57,14 @@ def _close_bf16(got, ref, absref, what):
 
 @pytest.mark.parametrize("N,H,W,Ci,Co,relu", [(2, 13, 70, 32, 64, 1), (1, 9, 130, 64, 96, 0),
                                               (3, 5, 17, 96, 32, 1), (1, 1, 1, 32, 32, 0),
-                                              # LDS-tiled kernel: 4 pixel tiles per wave
-                                              # (64 channels), 2 per wave (64 and 32 channels)
-                                              (8, 61, 67, 32, 256, 1), (4, 64, 64, 32, 128, 1),
-                                              (16, 61, 67, 32, 96, 0)])
+                                              # LDS-tiled kernel, 128-pixel blocks: 64- and
+                                              # 32-channel tiles
+                                              (8, 61, 67, 32, 256, 1), (16, 61, 67, 32, 96, 0),
+                                              # 64-pixel blocks (fewer than 512 of 128):
+                                              # 64- and 32-channel tiles, ragged tail,
+                                              # several input-channel chunks
+                                              (4, 64, 64, 32, 128, 1), (4, 61, 67, 32, 96, 1),
+                                              (4, 64, 96, 96, 64, 0), (1, 64, 128, 64, 256, 1)])
 def test_conv3x3_matches_reference(N, H, W, Ci, Co, relu):
     import torch
     x = _bf((N, H, W, Ci), 1)
