@@ -54,6 +54,14 @@ int fwi_nn_conv3x3(const void *x, const void *w, const float *bias, void *y, int
  * [Ci][3][3][Co], the weights of the transposed convolution. */
 int fwi_nn_flip(const void *w, void *wf, int32_t Ci, int32_t Co, void *stream);
 
+/* fwi_nn_flip for several layers in one launch: layer l's weights
+ * w + off[l] ([co[l]][3][3][ci[l]], in elements) go flipped to wf + off[l].
+ * off, ci, co: host arrays, read during the call; 1 <= nlayers <= 32, off
+ * ascending with the layers disjoint (off[l] + 9 ci[l] co[l] <= off[l+1]),
+ * 9 ci co < 2^31.  Elements of wf between the layers are not written. */
+int fwi_nn_flip_layers(const void *w, void *wf, int32_t nlayers, const int64_t *off,
+                       const int32_t *ci, const int32_t *co, void *stream);
+
 /* Weight and bias gradients of y = conv3x3(x, w) + b given dz = dL/dy:
  *   dw[co][ky][kx][ci] = sum over pixels p of dz[p][co] x[p + (ky-1, kx-1)][ci],
  *   db[co] = sum_p dz[p][co]   (float32 outputs, overwritten).

@@ -273,6 +273,32 @@ __global__ void k_flip(const bf16 *__restrict__ w, bf16 *__restrict__ wf, int Ci
     wf[((size_t)ci * 9 + (2 - ky) * 3 + (2 - kx)) * Co + co] = w[t];
 }
 
+// Several layers at once (one launch for the whole network): thread e writes
+// element e of wf when it lies in a layer, reading the matching weight of
+// w, so that the writes are coalesced.
+constexpr int kFlipMax = 32;
+struct FlipTable {
+    int n;
+    int64_t off[kFlipMax];
+    int32_t ci[kFlipMax], co[kFlipMax];
+};
+
+__global__ void k_flip_layers(const bf16 *__restrict__ w, bf16 *__restrict__ wf, FlipTable tb,
+                              int64_t end) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= end) return;
+    for (int l = 0; l < tb.n; ++l) {
+        const int64_t d = e - tb.off[l];
+        const int Ci = tb.ci[l], Co = tb.co[l];
+        if (d >= 0 && d < (int64_t)9 * Ci * Co) {
+            const int dd = (int)d;
+            const int co = dd % Co, k = (dd / Co) % 9, ci = dd / (9 * Co);
+            wf[e] = w[tb.off[l] + ((int64_t)co * 9 + (8 - k)) * Ci + ci];
+            return;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Weight and bias gradients: dw[co][ky][kx][ci] = sum_q dz[q][co] x[q + (ky-1, kx-1)][ci],
 // db[co] = sum_q dz[q][co].  A GEMM whose reduction runs over output pixels
@@ -687,6 +713,51 @@ __global__ __launch_bounds__(256) void k_mse(const bf16 *__restrict__ y,
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// The same loss per pixel, for C a multiple of 8 and 16-byte aligned rows:
+// a thread reads the cout channels of a pixel it needs and writes the whole
+// dy row as 16-byte pieces (zero past cout), with no per-element division.
+__global__ __launch_bounds__(256) void k_mse_px(const bf16 *__restrict__ y,
+                                                const float *__restrict__ tgt,
+                                                bf16 *__restrict__ dy,
+                                                double *__restrict__ partial, size_t P, int C,
+                                                int cout) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    const double scale = 2.0 / ((double)P * cout);
+    const int nv = C / 8;
+    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < P;
+         p += (size_t)gridDim.x * blockDim.x) {
+        for (int v = 0; v < nv; ++v) {
+            uint4 out = make_uint4(0u, 0u, 0u, 0u);
+            if (8 * v < cout) {
+                unsigned short h[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int c = 8 * v + e;
+                    float g = 0.f;
+                    if (c < cout) {
+                        const double d = (double)(float)y[p * C + c] - (double)tgt[p * cout + c];
+                        acc += d * d;
+                        g = (float)(scale * d);
+                    }
+                    const bf16 b = (bf16)g;
+                    h[e] = __builtin_bit_cast(unsigned short, b);
+                }
+                out = make_uint4(h[0] | (unsigned)h[1] << 16, h[2] | (unsigned)h[3] << 16,
+                                 h[4] | (unsigned)h[5] << 16, h[6] | (unsigned)h[7] << 16);
+            }
+            if (dy) *reinterpret_cast<uint4 *>(dy + p * C + 8 * v) = out;
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
 // *out = scale * sum of the partials: 64 strided sums, then a fixed-order
 // tree (deterministic)
 __global__ __launch_bounds__(64) void k_sum(const double *__restrict__ partial, int n,
@@ -734,6 +805,24 @@ __global__ void k_pack4(const float *__restrict__ planes, const float *__restric
     const size_t hw = (size_t)H * W;
     const size_t n = p / hw, q = p % hw;
     x[i] = c < 4 ? (bf16)(planes[(n * 4 + c) * hw + q] * scale[n * 4 + c]) : (bf16)0.f;
+}
+// The same packing per pixel for C a multiple of 8 and x 16-byte aligned:
+// four scaled plane values and zero padding, written as 16-byte pieces.
+__global__ void k_pack4_px(const float *__restrict__ planes, const float *__restrict__ scale,
+                           bf16 *__restrict__ x, int N, int H, int W, int C) {
+    const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t hw = (size_t)H * W;
+    if (p >= (size_t)N * hw) return;
+    const size_t n = p / hw, q = p - n * hw;
+    unsigned short h[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const bf16 b = (bf16)(planes[(n * 4 + c) * hw + q] * scale[n * 4 + c]);
+        h[c] = __builtin_bit_cast(unsigned short, b);
+    }
+    uint4 *row = reinterpret_cast<uint4 *>(x + p * C);
+    row[0] = make_uint4(h[0] | (unsigned)h[1] << 16, h[2] | (unsigned)h[3] << 16, 0u, 0u);
+    for (int v = 1; v < C / 8; ++v) row[v] = make_uint4(0u, 0u, 0u, 0u);
 }
 __global__ void k_unpack2(const bf16 *__restrict__ y, const float *__restrict__ scale,
                           float *__restrict__ out, int N, int H, int W, int C) {
@@ -805,6 +894,27 @@ int fwi_nn_flip(const void *w, void *wf, int32_t Ci, int32_t Co, void *stream) {
     const size_t n = (size_t)Co * 9 * Ci;
     hipLaunchKernelGGL(k_flip, dim3(blocks_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream),
                        static_cast<const bf16 *>(w), static_cast<bf16 *>(wf), Ci, Co);
+    return status(hipGetLastError());
+}
+
+int fwi_nn_flip_layers(const void *w, void *wf, int32_t nlayers, const int64_t *off,
+                       const int32_t *ci, const int32_t *co, void *stream) {
+    if (!w || !wf || !off || !ci || !co || nlayers < 1 || nlayers > kFlipMax)
+        return FWI_NN_EINVAL;
+    FlipTable tb{};
+    tb.n = nlayers;
+    int64_t end = 0;
+    for (int l = 0; l < nlayers; ++l) {
+        if (off[l] < end || ci[l] < 1 || co[l] < 1 || (int64_t)9 * ci[l] * co[l] >= (1ll << 31))
+            return FWI_NN_EINVAL;
+        tb.off[l] = off[l];
+        tb.ci[l] = ci[l];
+        tb.co[l] = co[l];
+        end = off[l] + (int64_t)9 * ci[l] * co[l];
+    }
+    hipLaunchKernelGGL(k_flip_layers, dim3(blocks_for((size_t)end)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), static_cast<const bf16 *>(w),
+                       static_cast<bf16 *>(wf), tb, end);
     return status(hipGetLastError());
 }
 
@@ -930,9 +1040,14 @@ int fwi_nn_mse(const void *y, const float *target, void *dy, double *loss, doubl
     if (!y || !target || !loss || !partials || P == 0 || C < 1 || cout < 1 || cout > C)
         return FWI_NN_EINVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(k_mse, dim3(FWI_NN_MSE_BLOCKS), dim3(256), 0, st,
-                       static_cast<const bf16 *>(y), target, static_cast<bf16 *>(dy), partials, P,
-                       C, cout);
+    if (C % 8 == 0 && (!dy || al16(dy)))
+        hipLaunchKernelGGL(k_mse_px, dim3(FWI_NN_MSE_BLOCKS), dim3(256), 0, st,
+                           static_cast<const bf16 *>(y), target, static_cast<bf16 *>(dy), partials,
+                           P, C, cout);
+    else
+        hipLaunchKernelGGL(k_mse, dim3(FWI_NN_MSE_BLOCKS), dim3(256), 0, st,
+                           static_cast<const bf16 *>(y), target, static_cast<bf16 *>(dy), partials,
+                           P, C, cout);
     hipLaunchKernelGGL(k_sum, dim3(1), dim3(64), 0, st, partials, FWI_NN_MSE_BLOCKS,
                        1.0 / ((double)P * cout), loss);
     return status(hipGetLastError());
@@ -960,9 +1075,14 @@ int fwi_nn_pack4(const float *planes, const float *scale, void *x, int32_t N, in
                  int32_t W, int32_t C, void *stream) {
     if (!planes || !scale || !x || N < 1 || H < 1 || W < 1 || C < 4) return FWI_NN_EINVAL;
     const size_t n = (size_t)N * H * W * C;
-    hipLaunchKernelGGL(k_pack4, dim3(blocks_for(n)), dim3(256), 0,
-                       static_cast<hipStream_t>(stream), planes, scale, static_cast<bf16 *>(x), N,
-                       H, W, C);
+    if (C % 8 == 0 && al16(x))
+        hipLaunchKernelGGL(k_pack4_px, dim3(blocks_for((size_t)N * H * W)), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), planes, scale,
+                           static_cast<bf16 *>(x), N, H, W, C);
+    else
+        hipLaunchKernelGGL(k_pack4, dim3(blocks_for(n)), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), planes, scale,
+                           static_cast<bf16 *>(x), N, H, W, C);
     return status(hipGetLastError());
 }
 

@@ -33,7 +33,8 @@ FWI_NN_OK = 0
 FWI_NN_MSE_BLOCKS = 512
 CPAD = 32                      # channels of the packed network input
 
-EXPORTED = ("fwi_nn_conv3x3", "fwi_nn_flip", "fwi_nn_wgrad_workspace", "fwi_nn_wgrad",
+EXPORTED = ("fwi_nn_conv3x3", "fwi_nn_flip", "fwi_nn_flip_layers", "fwi_nn_wgrad_workspace",
+            "fwi_nn_wgrad",
             "fwi_nn_relu_bwd", "fwi_nn_pool2", "fwi_nn_pool2_bwd", "fwi_nn_up2_add",
             "fwi_nn_up2_bwd", "fwi_nn_add", "fwi_nn_mse", "fwi_nn_adam", "fwi_nn_to_bf16",
             "fwi_nn_pack4", "fwi_nn_unpack2")
@@ -48,6 +49,7 @@ def lib() -> ctypes.CDLL:
         vp, sz, i32, f32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_float
         L.fwi_nn_conv3x3.argtypes = [vp, vp, vp, vp, i32, i32, i32, i32, i32, i32, vp]
         L.fwi_nn_flip.argtypes = [vp, vp, i32, i32, vp]
+        L.fwi_nn_flip_layers.argtypes = [vp, vp, i32, vp, vp, vp, vp]
         L.fwi_nn_wgrad_workspace.argtypes = [i32, i32, i32]
         L.fwi_nn_wgrad_workspace.restype = sz
         L.fwi_nn_wgrad.argtypes = [vp, vp, vp, vp, i32, i32, i32, i32, i32, i32, vp, sz, vp]
@@ -118,6 +120,20 @@ def flip(w, wf, Ci, Co, stream=None):
     _need(w, BF, Co * 9 * Ci, "w")
     _need(wf, BF, Co * 9 * Ci, "wf")
     _ok(lib().fwi_nn_flip(_p(w), _p(wf), Ci, Co, _s(stream)), "fwi_nn_flip")
+
+
+def flip_layers(w, wf, offs, cis, cos, stream=None):
+    """fwi_nn_flip for every (offset, Ci, Co) layer of the flat buffers w
+    and wf (bf16, same length) in one launch."""
+    n = len(offs)
+    _need(w, BF, w.numel(), "w")
+    _need(wf, BF, w.numel(), "wf")
+    if n and offs[-1] + 9 * cis[-1] * cos[-1] > w.numel():
+        raise ValueError("flip_layers: a layer runs past the end of w")
+    o = (ctypes.c_int64 * n)(*offs)
+    a = (ctypes.c_int32 * n)(*cis)
+    b = (ctypes.c_int32 * n)(*cos)
+    _ok(lib().fwi_nn_flip_layers(_p(w), _p(wf), n, o, a, b, _s(stream)), "fwi_nn_flip_layers")
 
 
 def wgrad_workspace(Ci, Co, nsplit):
@@ -299,8 +315,12 @@ class Net:
         self.step = 0
         self.offs = param_offsets()
         self._shape = None
-        self._wflip = torch.empty(max(ci * 9 * co for _, ci, co, _, _ in LAYERS), dtype=BF,
-                                  device=self.device)
+        # flipped weights of every layer but the first, at the offsets of
+        # the weights in wbf, made by one launch per backward pass
+        self._wflip = torch.empty(n, dtype=BF, device=self.device)
+        self._flip_table = ([self.offs[k][0] for k in range(1, len(LAYERS))],
+                            [LAYERS[k][1] for k in range(1, len(LAYERS))],
+                            [LAYERS[k][2] for k in range(1, len(LAYERS))])
         self.loss = torch.zeros(1, dtype=torch.float64, device=self.device)
         self.partials = torch.zeros(FWI_NN_MSE_BLOCKS, dtype=torch.float64, device=self.device)
 
@@ -420,6 +440,7 @@ class Net:
         def other(*used):
             return next(b for b in bufs if all(b is not u for u in used))
 
+        flip_layers(self.wbf, self._wflip, *self._flip_table)
         cur = dy
         for k in range(len(LAYERS) - 1, -1, -1):
             name, ci, co, lv, relu = LAYERS[k]
@@ -433,8 +454,8 @@ class Net:
                   self.nsplit[k], self.wsg)
             if k == 0:
                 break
-            wf = self._wflip[:ci * 9 * co]
-            flip(self.w(k), wf, ci, co)
+            wo = self.offs[k][0]
+            wf = self._wflip[wo:wo + ci * 9 * co]
             merge = name in ("d2a", "d1a", "d0a")
             dx = self.gskip[lv] if merge else other(dz, cur)
             conv3x3(dz, wf, None, dx, N, h, w, co, ci, False)

@@ -252,6 +252,17 @@ def test_nn_argument_checks():
     assert L.fwi_nn_conv3x3(A, A, None, A, 1, 32769, 1, 32, 32, 1, None) == E
     assert L.fwi_nn_conv3x3(A, A, None, A, 1, 1, 32769, 32, 32, 1, None) == E
     assert L.fwi_nn_wgrad(A, A, A, A, 1, 1, 32769, 32, 64, 4, A, 1 << 30, None) == E
+    # several layers' flips: table checks (layers ascending and disjoint)
+    I64, I32 = ctypes.c_int64, ctypes.c_int32
+    off, ci, co = (I64 * 2)(0, 9 * 32 * 32), (I32 * 2)(32, 32), (I32 * 2)(32, 64)
+    assert L.fwi_nn_flip_layers(A, A, 0, off, ci, co, None) == E
+    assert L.fwi_nn_flip_layers(A, A, 33, off, ci, co, None) == E
+    assert L.fwi_nn_flip_layers(None, A, 2, off, ci, co, None) == E
+    assert L.fwi_nn_flip_layers(A, A, 2, None, ci, co, None) == E
+    bad = (I64 * 2)(0, 9 * 32 * 32 - 1)
+    assert L.fwi_nn_flip_layers(A, A, 2, bad, ci, co, None) == E
+    assert L.fwi_nn_flip_layers(A, A, 2, (I64 * 2)(-1, 10000), ci, co, None) == E
+    assert L.fwi_nn_flip_layers(A, A, 2, off, ci, (I32 * 2)(32, 0), None) == E
     # weight gradient: workspace size and split count
     need = L.fwi_nn_wgrad_workspace(32, 64, 4)
     assert need == (4 * 64 * 9 * 32 + 4 * 64) * 4

@@ -94,6 +94,24 @@ def test_flipped_conv_is_the_input_gradient():
     _close_bf16(dx.view(N, H, W, Ci), x.grad, aref, "input gradient")
 
 
+def test_flip_layers_matches_per_layer_flips():
+    """One launch for every layer but the first, against fwi_nn_flip per
+    layer; elements between the layers (bias and alignment slots) keep what
+    they held."""
+    import torch
+    net = nn.Net(seed=3)
+    wf = torch.full_like(net.wbf, 7.0)
+    offs, cis, cos = net._flip_table
+    nn.flip_layers(net.wbf, wf, offs, cis, cos)
+    ref = torch.full_like(net.wbf, 7.0)
+    for k in range(1, len(nn.LAYERS)):
+        _, ci, co, _, _ = nn.LAYERS[k]
+        wo = net.offs[k][0]
+        nn.flip(net.w(k), ref[wo:wo + co * 9 * ci], ci, co)
+    torch.cuda.synchronize()
+    assert torch.equal(wf.cpu(), ref.cpu())
+
+
 @pytest.mark.parametrize("N,H,W,Ci,Co,nsplit", [(2, 10, 37, 32, 64, 1), (2, 10, 37, 32, 64, 3),
                                                  (2, 10, 37, 32, 64, 700),
                                                  # chunks crossing rows and images, odd width
@@ -193,6 +211,19 @@ def test_mse_adam_pack_unpack():
     g[:, :cout] = R.rb((2 * d / (P * cout)).float()).double()
     got = dy.double().cpu().view(P, C)
     assert float(((got - g).abs() / (2 ** -8 * g.abs() + 1e-30)).max()) <= 1.0
+    # the element-wise form (channel count not a multiple of 8)
+    P2, C2, c2 = 37, 5, 3
+    y2 = _bf((P2, C2), 18)
+    t2 = torch.randn(P2, c2, generator=torch.Generator().manual_seed(19), dtype=torch.float64).float()
+    dy2 = torch.empty(P2 * C2, dtype=torch.bfloat16, device="cuda")
+    nn.mse(_dev(y2), _dev(t2), dy2, loss, part, P2, C2, c2)
+    torch.cuda.synchronize()
+    d2 = y2.double()[:, :c2] - t2.double()
+    assert abs(float(loss) - float((d2 * d2).mean())) <= 1e-12 * float((d2 * d2).mean())
+    g2 = torch.zeros(P2, C2, dtype=torch.float64)
+    g2[:, :c2] = R.rb((2 * d2 / (P2 * c2)).float()).double()
+    got2 = dy2.double().cpu().view(P2, C2)
+    assert float(((got2 - g2).abs() / (2 ** -8 * g2.abs() + 1e-30)).max()) <= 1.0
     # Adam, two steps, against the textbook update in float64
     n = 1000
     gen = torch.Generator().manual_seed(15)
