@@ -83,6 +83,11 @@ int fwi_nn_relu_bwd(const void *y, const void *dy, void *dz, size_t n, void *str
 int fwi_nn_pool2(const void *x, void *y, int32_t N, int32_t H, int32_t W, int32_t C, void *stream);
 int fwi_nn_pool2_bwd(const void *dy, void *dx, int32_t N, int32_t H, int32_t W, int32_t C,
                      void *stream);
+/* The adjoint of the pooling plus a skip gradient: dx = pool2_bwd(dy) + skip,
+ * skip [N][H][W][C] (NULL = none), rounded to bf16 once, the same values as
+ * fwi_nn_pool2_bwd followed by fwi_nn_add. */
+int fwi_nn_pool2_bwd_add(const void *dy, const void *skip, void *dx, int32_t N, int32_t H,
+                         int32_t W, int32_t C, void *stream);
 
 /* y [N][Ho][Wo][C] = nearest 2x upsampling of x [N][Ho/2][Wo/2][C] plus
  * skip [N][Ho][Wo][C] (NULL = no skip); fwi_nn_up2_bwd is the adjoint of

@@ -535,15 +535,17 @@ __global__ void k_pool(const bf16 *__restrict__ x, bf16 *__restrict__ y, int N, 
     const float s = (float)p[0] + (float)p[C] + (float)p[(size_t)W * C] + (float)p[(size_t)W * C + C];
     y[i] = (bf16)(0.25f * s);
 }
-__global__ void k_pool_bwd(const bf16 *__restrict__ dy, bf16 *__restrict__ dx, int N, int H,
-                           int W, int C) {
+__global__ void k_pool_bwd(const bf16 *__restrict__ dy, const bf16 *__restrict__ s,
+                           bf16 *__restrict__ dx, int N, int H, int W, int C) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (size_t)N * H * W * C) return;
     const int c = (int)(i % C);
     size_t r = i / C;
     const int xx = (int)(r % W), yy = (int)((r / W) % H);
     const size_t n = r / ((size_t)W * H);
-    dx[i] = (bf16)(0.25f * (float)dy[((n * (H / 2) + yy / 2) * (W / 2) + xx / 2) * C + c]);
+    float v = 0.25f * (float)dy[((n * (H / 2) + yy / 2) * (W / 2) + xx / 2) * C + c];
+    if (s) v += (float)s[i];
+    dx[i] = (bf16)v;
 }
 
 // nearest 2x upsampling plus a skip: y = up(x) + s (s may be null), and the
@@ -625,8 +627,8 @@ __global__ void k_pool8(const bf16 *__restrict__ x, bf16 *__restrict__ y, int N,
     st8(y + r * C + c, o);
 }
 
-__global__ void k_pool_bwd8(const bf16 *__restrict__ dy, bf16 *__restrict__ dx, int N, int H,
-                            int W, int C) {
+__global__ void k_pool_bwd8(const bf16 *__restrict__ dy, const bf16 *__restrict__ s,
+                            bf16 *__restrict__ dx, int N, int H, int W, int C) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int C8 = C / 8;
     if (i >= (size_t)N * H * W * C8) return;
@@ -636,8 +638,14 @@ __global__ void k_pool_bwd8(const bf16 *__restrict__ dy, bf16 *__restrict__ dx, 
     const size_t n = r / ((size_t)W * H);
     const bf16x8 g = ld8(dy + ((n * (H / 2) + yy / 2) * (W / 2) + xx / 2) * C + c);
     bf16x8 o;
+    if (s) {
+        const bf16x8 v = ld8(s + r * C + c);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) o[k] = (bf16)(0.25f * (float)g[k]);
+        for (int k = 0; k < 8; ++k) o[k] = (bf16)(0.25f * (float)g[k] + (float)v[k]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) o[k] = (bf16)(0.25f * (float)g[k]);
+    }
     st8(dx + r * C + c, o);
 }
 
@@ -976,19 +984,25 @@ int fwi_nn_pool2(const void *x, void *y, int32_t N, int32_t H, int32_t W, int32_
     return status(hipGetLastError());
 }
 
-int fwi_nn_pool2_bwd(const void *dy, void *dx, int32_t N, int32_t H, int32_t W, int32_t C,
-                     void *stream) {
+int fwi_nn_pool2_bwd_add(const void *dy, const void *skip, void *dx, int32_t N, int32_t H,
+                         int32_t W, int32_t C, void *stream) {
     if (!dy || !dx || N < 1 || H < 2 || W < 2 || H % 2 || W % 2 || C < 1) return FWI_NN_EINVAL;
     const size_t n = (size_t)N * H * W * C;
-    if (C % 8 == 0 && al16(dy) && al16(dx))
+    const bf16 *sb = static_cast<const bf16 *>(skip);
+    if (C % 8 == 0 && al16(dy) && al16(dx) && (!skip || al16(skip)))
         hipLaunchKernelGGL(k_pool_bwd8, dim3(blocks_for(n / 8)), dim3(256), 0,
-                           static_cast<hipStream_t>(stream), static_cast<const bf16 *>(dy),
+                           static_cast<hipStream_t>(stream), static_cast<const bf16 *>(dy), sb,
                            static_cast<bf16 *>(dx), N, H, W, C);
     else
         hipLaunchKernelGGL(k_pool_bwd, dim3(blocks_for(n)), dim3(256), 0,
-                           static_cast<hipStream_t>(stream), static_cast<const bf16 *>(dy),
+                           static_cast<hipStream_t>(stream), static_cast<const bf16 *>(dy), sb,
                            static_cast<bf16 *>(dx), N, H, W, C);
     return status(hipGetLastError());
+}
+
+int fwi_nn_pool2_bwd(const void *dy, void *dx, int32_t N, int32_t H, int32_t W, int32_t C,
+                     void *stream) {
+    return fwi_nn_pool2_bwd_add(dy, nullptr, dx, N, H, W, C, stream);
 }
 
 int fwi_nn_up2_add(const void *x, const void *skip, void *y, int32_t N, int32_t Ho, int32_t Wo,

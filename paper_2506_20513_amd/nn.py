@@ -35,7 +35,8 @@ CPAD = 32                      # channels of the packed network input
 
 EXPORTED = ("fwi_nn_conv3x3", "fwi_nn_flip", "fwi_nn_flip_layers", "fwi_nn_wgrad_workspace",
             "fwi_nn_wgrad",
-            "fwi_nn_relu_bwd", "fwi_nn_pool2", "fwi_nn_pool2_bwd", "fwi_nn_up2_add",
+            "fwi_nn_relu_bwd", "fwi_nn_pool2", "fwi_nn_pool2_bwd", "fwi_nn_pool2_bwd_add",
+            "fwi_nn_up2_add",
             "fwi_nn_up2_bwd", "fwi_nn_add", "fwi_nn_mse", "fwi_nn_adam", "fwi_nn_to_bf16",
             "fwi_nn_pack4", "fwi_nn_unpack2")
 
@@ -56,6 +57,7 @@ def lib() -> ctypes.CDLL:
         L.fwi_nn_relu_bwd.argtypes = [vp, vp, vp, sz, vp]
         L.fwi_nn_pool2.argtypes = [vp, vp, i32, i32, i32, i32, vp]
         L.fwi_nn_pool2_bwd.argtypes = [vp, vp, i32, i32, i32, i32, vp]
+        L.fwi_nn_pool2_bwd_add.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp]
         L.fwi_nn_up2_add.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp]
         L.fwi_nn_up2_bwd.argtypes = [vp, vp, i32, i32, i32, i32, vp]
         L.fwi_nn_add.argtypes = [vp, vp, vp, sz, vp]
@@ -165,6 +167,16 @@ def pool2_bwd(dy, dx, N, H, W, C, stream=None):
     _need(dy, BF, N * (H // 2) * (W // 2) * C, "dy")
     _need(dx, BF, N * H * W * C, "dx")
     _ok(lib().fwi_nn_pool2_bwd(_p(dy), _p(dx), N, H, W, C, _s(stream)), "fwi_nn_pool2_bwd")
+
+
+def pool2_bwd_add(dy, skip, dx, N, H, W, C, stream=None):
+    """dx = pool2_bwd(dy) + skip (skip may be None)."""
+    _need(dy, BF, N * (H // 2) * (W // 2) * C, "dy")
+    if skip is not None:
+        _need(skip, BF, N * H * W * C, "skip")
+    _need(dx, BF, N * H * W * C, "dx")
+    _ok(lib().fwi_nn_pool2_bwd_add(_p(dy), _p(skip), _p(dx), N, H, W, C, _s(stream)),
+        "fwi_nn_pool2_bwd_add")
 
 
 def up2_add(x, skip, y, N, Ho, Wo, C, stream=None):
@@ -462,8 +474,7 @@ class Net:
             if name in ("e1a", "e2a", "e3a"):
                 hp, wp = hw[lv - 1]
                 g = other(dx)
-                pool2_bwd(dx, g, N, hp, wp, ci)
-                add(g, self.gskip[lv - 1], g, N * hp * wp * ci)
+                pool2_bwd_add(dx, self.gskip[lv - 1], g, N, hp, wp, ci)
                 cur = g
             elif merge:
                 hi, wi = hw[lv + 1]

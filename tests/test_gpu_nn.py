@@ -159,6 +159,10 @@ def test_elementwise_kernels_match_reference(C):
     dx = torch.empty(N * H * W * C, dtype=torch.bfloat16, device="cuda")
     nn.pool2_bwd(dev(q), dx, N, H, W, C)
     ref_b = R.nhwc(F.interpolate(R.nchw(q.double()), scale_factor=2, mode="nearest") * 0.25)
+    dxs = torch.empty_like(dx)
+    nn.pool2_bwd_add(dev(q), dev(s), dxs, N, H, W, C)
+    dx2 = torch.empty_like(dx)
+    nn.add(dx, dev(s), dx2, x.numel())
     # upsampling + skip and its adjoint
     u = torch.empty(N * H * W * C, dtype=torch.bfloat16, device="cuda")
     nn.up2_add(dev(q), dev(s), u, N, H, W, C)
@@ -175,7 +179,10 @@ def test_elementwise_kernels_match_reference(C):
     a = torch.empty_like(dx)
     nn.add(dev(x), dev(s), a, x.numel())
     torch.cuda.synchronize()
-    cases = [(y, ref, "pool"), (dx, ref_b, "pool adjoint"), (u, ref_u, "up + skip"),
+    # fused adjoint + skip: the same bf16 values as the two calls
+    assert torch.equal(dxs.cpu(), dx2.cpu())
+    cases = [(y, ref, "pool"), (dx, ref_b, "pool adjoint"), (dxs, ref_b + s.double(), "pool adjoint + skip"),
+             (u, ref_u, "up + skip"),
              (u0, R.nhwc(F.interpolate(R.nchw(q.double()), scale_factor=2, mode="nearest")), "up"),
              (du, ref_du, "up adjoint"), (dz, ref_dz, "relu backward"),
              (a, x.double() + s.double(), "add")]
