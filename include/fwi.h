@@ -55,6 +55,9 @@
  *   is fwi_gradient_static, whose workspace is a static device array of the
  *   library (see there).
  * - Every call runs on `stream` (a hipStream_t; NULL = the null stream).
+ *   A gradient call that splits its shots into groups (fwi_gradient_ex)
+ *   also creates one non-blocking stream per group and a few events, joins
+ *   them to `stream` and destroys them before it returns.
  *   Host arrays may be reused as soon as the call returns.  The forward,
  *   adjoint and gradient calls return once the stream has finished them
  *   (see Errors); the batched runs are asynchronous, and their device
@@ -201,6 +204,8 @@ typedef struct fwi_timing {
     int32_t sample_every;      /* in: >= 1                                   */
     int32_t nkinds;            /* out: entries filled in `kind`               */
     fwi_kernel_time kind[FWI_TIMING_MAX_KINDS];
+    int32_t shot_groups;       /* out: shot groups the call ran in (each
+                                  launch covers one group's shots)           */
 } fwi_timing;
 
 /* fwi_gradient with per-kernel timing.  timing: host in/out, or NULL (then
@@ -211,6 +216,29 @@ int fwi_gradient_timed(const fwi_grid *grid, const fwi_geom *geom,
                        const float *observed, double *misfit, float *grad_eps_r,
                        float *grad_sigma, float *traces_out, void *ws,
                        size_t ws_bytes, void *stream, fwi_timing *timing);
+
+/* fwi_gradient (with optional timing) whose shots run in shot_groups groups
+ * of consecutive shots, each group's forward and adjoint passes on a stream
+ * of its own, so that the groups' launches overlap on the GPU.  The
+ * coefficient setup, the residual and misfit of all shots and the final
+ * gradient (a sum over all shots in shot order) run on `stream` between
+ * the groups' phases, so the results are identical bit for bit for every
+ * group count.  shot_groups: 0 = automatic (with 16 or more shots one group
+ * per 8 shots, at most 3: the 64-shot 2088 x 1064 gradient measured 11%
+ * faster in 2 or 3 groups than in one, the 24-shot 552 x 296 one 6% faster
+ * in 3; 1 group below 16 shots), 1 .. 4 = that many (at most nshots; 4
+ * groups were slower than 3 under the runtime's default of four hardware
+ * queues per process).  fwi_workspace_bytes(..., -1, ...) covers every
+ * group count.  With timing, each kind's launches of all groups are
+ * counted and timed; their durations include the other groups' launches
+ * running beside them.  FWI_EINVAL if shot_groups is outside 0 .. 4.
+ * fwi_gradient and fwi_gradient_timed are this call with shot_groups = 0. */
+int fwi_gradient_ex(const fwi_grid *grid, const fwi_geom *geom,
+                    const float *eps_r, const float *sigma,
+                    const float *observed, double *misfit, float *grad_eps_r,
+                    float *grad_sigma, float *traces_out, void *ws,
+                    size_t ws_bytes, void *stream, fwi_timing *timing,
+                    int32_t shot_groups);
 
 /* ---- Allocation-free gradient -------------------------------------------
  * For callers that cannot allocate device memory (code under HIP graph
@@ -226,7 +254,9 @@ int fwi_gradient_timed(const fwi_grid *grid, const fwi_geom *geom,
  * device.  All calls on one device share its array: calls that overlap in
  * time on one device race and must be ordered by the caller (one stream, or
  * events).  Results equal fwi_gradient's bit for bit.  Like fwi_gradient,
- * the call synchronises `stream` once while it uploads the geometry. */
+ * the call synchronises `stream` once while it uploads the geometry.  It
+ * runs all shots as one group (fwi_gradient_ex with shot_groups = 1), so it
+ * creates no streams or events. */
 #define FWI_STATIC_SCRATCH_BYTES (64u << 20)
 int fwi_gradient_static(const fwi_grid *grid, const fwi_geom *geom,
                         const float *eps_r, const float *sigma,

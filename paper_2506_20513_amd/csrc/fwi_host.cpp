@@ -159,26 +159,38 @@ void fixed_bands(Layout &L, int rows, int depth) {
     L.bands[nb] = L.abands[nb] = L.d.NY;
 }
 
-// Workspace layout for a mode (FWI_SAVE_* or -1 = fwi_gradient).
-int make_layout(const Dims &d, int mode, Layout &L, int k, int depth) {
+// Workspace layout for a mode (FWI_SAVE_* or -1 = fwi_gradient).  With
+// `shared` (gradient mode only), the layout is one shot group's: it starts
+// at byte `start`, and its coefficients, profiles, imaging sums, traces,
+// residual and reduction partials are those of `shared` (the sums, traces
+// and residual at the group's first shot s0).
+int make_layout(const Dims &d, int mode, Layout &L, int k, int depth, size_t start,
+                const Layout *shared, int s0) {
     if (mode != FWI_SAVE_NONE && mode != FWI_SAVE_CHECKPOINT &&
         mode != FWI_SAVE_HISTORY && mode != -1)
         return FWI_EINVAL;
+    if (shared && mode != -1) return FWI_EINVAL;
     L.d = d;
     L.mode = mode;
     L.depth = depth > 0 ? depth : stream_depth(d);
     const size_t S = (size_t)d.S;
     const size_t field = S * d.plane * sizeof(float);
     const size_t xs = S * d.xs * sizeof(float), ys = S * d.ys * sizeof(float);
-    size_t off = 0;
+    size_t off = start;
     auto take = [&](size_t bytes) {
         size_t o = off;
         off += align_up(bytes);
         return o;
     };
-    L.off_Ca = take(d.plane * sizeof(float));
-    L.off_Cs = take(d.plane * sizeof(float));
-    L.off_prof = take((size_t)6 * (d.NX + d.NY) * sizeof(float));
+    if (shared) {
+        L.off_Ca = shared->off_Ca;
+        L.off_Cs = shared->off_Cs;
+        L.off_prof = shared->off_prof;
+    } else {
+        L.off_Ca = take(d.plane * sizeof(float));
+        L.off_Cs = take(d.plane * sizeof(float));
+        L.off_prof = take((size_t)6 * (d.NX + d.NY) * sizeof(float));
+    }
     L.off_src = take(S * 2 * sizeof(int));
     L.off_rrow = take(S * (d.NY + 1) * sizeof(int));
     L.off_rcol = take(S * d.R * sizeof(int));
@@ -213,19 +225,105 @@ int make_layout(const Dims &d, int mode, Layout &L, int k, int depth) {
     if (mode != FWI_SAVE_NONE) {
         L.off_adj[0] = take(align_up(field) + L.state_bytes);
         L.off_adj[1] = take(align_up(field) + L.state_bytes);
-        L.off_S1 = take(field);
-        L.off_S2 = take(field);
+        if (!shared) {
+            L.off_S1 = take(field);
+            L.off_S2 = take(field);
+        }
     }
     L.off_res = L.off_trc = L.off_mis = 0;
-    if (mode == -1) {
-        const size_t tr = S * d.R * (size_t)d.nt * sizeof(float);
-        L.off_res = take(tr);
-        L.off_trc = take(tr);
-        L.off_mis = take(kMisfitBlocks * sizeof(double));
+    if (shared) {
+        const size_t sp = (size_t)s0 * d.plane * sizeof(float);
+        const size_t st = (size_t)s0 * d.R * (size_t)d.nt * sizeof(float);
+        L.off_S1 = shared->off_S1 + sp;
+        L.off_S2 = shared->off_S2 + sp;
+        L.off_res = shared->off_res + st;
+        L.off_trc = shared->off_trc + st;
+        L.off_mis = shared->off_mis;
+        L.off_chk = shared->off_chk;
+    } else {
+        if (mode == -1) {
+            const size_t tr = S * d.R * (size_t)d.nt * sizeof(float);
+            L.off_res = take(tr);
+            L.off_trc = take(tr);
+            L.off_mis = take(kMisfitBlocks * sizeof(double));
+        }
+        L.off_chk = take(kMisfitBlocks * sizeof(double) + sizeof(int));
     }
-    L.off_chk = take(kMisfitBlocks * sizeof(double) + sizeof(int));
     L.total = off;
     make_tiling(d, L);
+    return FWI_OK;
+}
+
+// The gradient's shots in G groups (shots s0[g] .. s0[g+1]-1) that run
+// concurrently, each on its own stream: the arrays that every group reads
+// (coefficients, profiles) or that a step after the groups reads across all
+// shots (imaging sums, traces, residual, reduction partials) once, laid out
+// as a full layout would, then each group's own layout (geometry tables,
+// states, Ez slots, checkpoints).  Every shot's arithmetic is the same as in
+// a single group, so the results are identical bit for bit.
+int make_group_layout(const Dims &d, int G, GroupLayout &GL) {
+    if (G < 1 || G > kMaxShotGroups || G > d.S) return FWI_EINVAL;
+    GL.G = G;
+    Layout &sh = GL.shared;
+    sh = Layout{};
+    sh.d = d;
+    sh.mode = -1;
+    const size_t S = (size_t)d.S;
+    const size_t field = S * d.plane * sizeof(float);
+    const size_t tr = S * d.R * (size_t)d.nt * sizeof(float);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    sh.off_Ca = take(d.plane * sizeof(float));
+    sh.off_Cs = take(d.plane * sizeof(float));
+    sh.off_prof = take((size_t)6 * (d.NX + d.NY) * sizeof(float));
+    sh.off_S1 = take(field);
+    sh.off_S2 = take(field);
+    sh.off_res = take(tr);
+    sh.off_trc = take(tr);
+    sh.off_mis = take(kMisfitBlocks * sizeof(double));
+    sh.off_chk = take(kMisfitBlocks * sizeof(double) + sizeof(int));
+    for (int g = 0; g <= G; ++g) GL.s0[g] = (int)((long long)g * d.S / G);
+    for (int g = 0; g < G; ++g) {
+        Dims dg = d;
+        dg.S = GL.s0[g + 1] - GL.s0[g];
+        const int rc = make_layout(dg, -1, GL.grp[g], 0, 0, off, &sh, GL.s0[g]);
+        if (rc != FWI_OK) return rc;
+        off = GL.grp[g].total;
+    }
+    sh.total = off;
+    GL.total = off;
+    return FWI_OK;
+}
+
+// Shot groups of a gradient call: with 16 or more shots, one group per 8
+// shots up to three; one group otherwise.  The groups' launches fill each
+// other's last, partial rounds of waves and hide each other's pipeline
+// starts.  Measured (one group -> two -> three -> four): 2088 x 1064 cells,
+// 64 shots: 5.60 -> 4.97 -> 4.96 -> 5.63 s; 552 x 296 cells, 24 shots:
+// 0.175 -> 0.177 -> 0.164 -> 0.225 s.  Four group streams exceed the four
+// hardware queues a process gets by default, so two groups share a queue
+// and run one after the other.
+int auto_shot_groups(const Dims &d) {
+    return d.S >= 16 ? std::min(3, d.S / 8) : 1;
+}
+
+// Gradient workspace: enough for one group and for every group count up to
+// kMaxShotGroups (the groups add only small per-group tables).
+int gradient_workspace(const Dims &d, size_t &bytes) {
+    Layout L;
+    int rc = make_layout(d, -1, L);
+    if (rc != FWI_OK) return rc;
+    bytes = L.total;
+    for (int G = 2; G <= kMaxShotGroups && G <= d.S; ++G) {
+        GroupLayout GL;
+        rc = make_group_layout(d, G, GL);
+        if (rc != FWI_OK) return rc;
+        bytes = std::max(bytes, GL.total);
+    }
     return FWI_OK;
 }
 
@@ -449,10 +547,9 @@ struct Timer {
         return e;
     }
 
-    int finish() {
-        if (!t) return FWI_OK;
-        double sum[K_NKINDS] = {0, 0, 0};
-        int cnt[K_NKINDS] = {0, 0, 0};
+    // Wait for the stream, add the sampled launches' durations to sum / cnt
+    // and release the events.
+    int collect(double *sum, int *cnt) {
         int rc = FWI_OK;
         if (hipStreamSynchronize(st) != hipSuccess) rc = FWI_EHIP;
         for (auto &r : recs) {
@@ -465,6 +562,20 @@ struct Timer {
             (void)hipEventDestroy(r.b);
         }
         recs.clear();
+        return rc;
+    }
+
+    int finish() {
+        if (!t) return FWI_OK;
+        double sum[K_NKINDS] = {0, 0, 0};
+        int cnt[K_NKINDS] = {0, 0, 0};
+        const int rc = collect(sum, cnt);
+        report(t, launches, updates, sum, cnt);
+        return rc;
+    }
+
+    static void report(fwi_timing *t, const int *launches, const double *updates,
+                       const double *sum, const int *cnt) {
         t->nkinds = K_NKINDS;
         for (int k = 0; k < K_NKINDS; ++k) {
             fwi_kernel_time &o = t->kind[k];
@@ -475,7 +586,6 @@ struct Timer {
             o.avg_ms = cnt[k] ? sum[k] / cnt[k] : 0.0;
             o.cell_updates = updates[k];
         }
-        return rc;
     }
 };
 
@@ -520,19 +630,16 @@ int forward_passes(const Ptrs &P, FwdStreamArgs a, int n0, int n1, int &cur, EIn
     return FWI_OK;
 }
 
-int do_forward(const Layout &L, const fwi_geom *g, const StreamCold &cold,
-               const float *eps_r, const float *sigma, void *ws, hipStream_t st,
-               Timer &tm) {
+// The forward time loop on a workspace whose coefficients, profiles and
+// geometry are in place (record: the traces are written).
+int forward_run(const Layout &L, void *ws, bool record, hipStream_t st, Timer &tm) {
     const Dims &d = L.d;
     Ptrs P{static_cast<char *>(ws), &L};
-    int rc = setup(P, g, cold, eps_r, sigma, st);
-    if (rc != FWI_OK) return rc;
     State fs0 = P.state(L.off_fwd[0], false);
-    rc = zero_state(fs0, d, false, st);
+    int rc = zero_state(fs0, d, false, st);
     if (rc != FWI_OK) return rc;
     FWI_TRY(launch_fill(P.slot(0), (size_t)d.S * d.plane, 0.f, st));
     FwdStreamArgs a = fwd_args(P);
-    const bool record = cold.traces != nullptr;
     int cur = 0;
     if (L.mode == FWI_SAVE_HISTORY) {
         return forward_passes(
@@ -567,8 +674,19 @@ int do_forward(const Layout &L, const fwi_geom *g, const StreamCold &cold,
     return FWI_OK;
 }
 
+int do_forward(const Layout &L, const fwi_geom *g, const StreamCold &cold,
+               const float *eps_r, const float *sigma, void *ws, hipStream_t st,
+               Timer &tm) {
+    Ptrs P{static_cast<char *>(ws), &L};
+    const int rc = setup(P, g, cold, eps_r, sigma, st);
+    if (rc != FWI_OK) return rc;
+    return forward_run(L, ws, cold.traces != nullptr, st, tm);
+}
+
+// The adjoint time loop and imaging; with finalize, the gradients from the
+// imaging sums of the layout's shots.
 int do_adjoint(const Layout &L, const float *eps_r, const float *sigma, float *g_eps,
-               float *g_sig, void *ws, hipStream_t st, Timer &tm) {
+               float *g_sig, void *ws, hipStream_t st, Timer &tm, bool finalize = true) {
     const Dims &d = L.d;
     Ptrs P{static_cast<char *>(ws), &L};
     State as[2] = {P.state(L.off_adj[0], true), P.state(L.off_adj[1], true)};
@@ -629,9 +747,122 @@ int do_adjoint(const Layout &L, const float *eps_r, const float *sigma, float *g
             if (rc != FWI_OK) return rc;
         }
     }
-    FWI_TRY(launch_gradient_finalize(eps_r, sigma, S1, S2, d.S, d.plane, g_eps, g_sig,
-                                     d.NX, d.NY, d.pitch, d.dt, st));
+    if (finalize)
+        FWI_TRY(launch_gradient_finalize(eps_r, sigma, S1, S2, d.S, d.plane, g_eps, g_sig,
+                                         d.NX, d.NY, d.pitch, d.dt, st));
     return FWI_OK;
+}
+
+// fwi_gradient over G >= 2 shot groups, each on a stream of its own (see
+// make_group_layout): shot-independent setup and each group's geometry on
+// the caller's stream; the groups' forward sweeps; the residual and misfit
+// of all shots; the groups' adjoint passes; the gradients from all shots'
+// imaging sums in shot order.  The streams join the caller's at each of
+// these steps.
+int gradient_groups(const Dims &d, int G, const fwi_geom *geom, const float *eps_r,
+                    const float *sigma, const float *observed, double *misfit, float *g_eps,
+                    float *g_sig, float *traces_out, void *ws, hipStream_t st,
+                    fwi_timing *timing) {
+    GroupLayout GL;
+    int rc = make_group_layout(d, G, GL);
+    if (rc != FWI_OK) return rc;
+    char *base = static_cast<char *>(ws);
+    const Layout &sh = GL.shared;
+    Ptrs PS{base, &sh};
+    float *traces = traces_out ? traces_out : PS.f(sh.off_trc);
+    float *res = PS.f(sh.off_res);
+    FWI_TRY(launch_coefficients(eps_r, sigma, PS.f(sh.off_Ca), PS.f(sh.off_Cs), d.NX, d.NY,
+                                d.pitch, d.dt, st));
+    FWI_TRY(launch_profiles(d, PS.prof(), st));
+    fwi_geom gg[kMaxShotGroups];
+    for (int g = 0; g < G; ++g) {
+        const int s0 = GL.s0[g];
+        gg[g] = *geom;
+        gg[g].nshots = GL.s0[g + 1] - s0;
+        gg[g].src_ij = geom->src_ij + 2 * (size_t)s0;
+        gg[g].rec_ij = geom->rec_ij + 2 * (size_t)s0 * d.R;
+        gg[g].wavelet = geom->wavelet + (size_t)s0 * d.nt;
+        Ptrs P{base, &GL.grp[g]};
+        const size_t t0 = (size_t)s0 * d.nt * d.R;
+        const StreamCold cold = make_cold(P, &gg[g], traces + t0, res + t0, nullptr);
+        rc = upload_geometry(P, &gg[g], cold, st);
+        if (rc != FWI_OK) return rc;
+    }
+    hipStream_t gs[kMaxShotGroups] = {};
+    hipEvent_t ev[kMaxShotGroups + 1] = {};
+    Timer tm[kMaxShotGroups];
+    for (int g = 0; g < G && rc == FWI_OK; ++g)
+        if (hipStreamCreateWithFlags(&gs[g], hipStreamNonBlocking) != hipSuccess) rc = FWI_EHIP;
+    for (int e = 0; e <= G && rc == FWI_OK; ++e)
+        if (hipEventCreateWithFlags(&ev[e], hipEventDisableTiming) != hipSuccess) rc = FWI_EHIP;
+    for (int g = 0; g < G; ++g) {
+        tm[g].t = timing;
+        tm[g].st = gs[g];
+    }
+    auto fork = [&]() -> int {
+        FWI_TRY(hipEventRecord(ev[G], st));
+        for (int g = 0; g < G; ++g) FWI_TRY(hipStreamWaitEvent(gs[g], ev[G], 0));
+        return FWI_OK;
+    };
+    // joins every group stream, also after a failed step
+    auto join = [&]() -> int {
+        int r = FWI_OK;
+        for (int g = 0; g < G; ++g) {
+            if (!gs[g] || !ev[g]) continue;
+            if (hipEventRecord(ev[g], gs[g]) != hipSuccess ||
+                hipStreamWaitEvent(st, ev[g], 0) != hipSuccess)
+                r = FWI_EHIP;
+        }
+        return r;
+    };
+    if (rc == FWI_OK) {
+        rc = fork();
+        for (int g = 0; g < G && rc == FWI_OK; ++g)
+            rc = forward_run(GL.grp[g], ws, true, gs[g], tm[g]);
+        const int rj = join();
+        if (rc == FWI_OK) rc = rj;
+    }
+    if (rc == FWI_OK &&
+        launch_residual_misfit(traces, observed, res, (size_t)d.S * d.nt * d.R,
+                               reinterpret_cast<double *>(base + sh.off_mis), misfit,
+                               st) != hipSuccess)
+        rc = FWI_EHIP;
+    if (rc == FWI_OK) {
+        rc = fork();
+        for (int g = 0; g < G && rc == FWI_OK; ++g)
+            rc = do_adjoint(GL.grp[g], eps_r, sigma, nullptr, nullptr, ws, gs[g], tm[g], false);
+        const int rj = join();
+        if (rc == FWI_OK) rc = rj;
+    }
+    if (rc == FWI_OK &&
+        launch_gradient_finalize(eps_r, sigma, PS.f(sh.off_S1), PS.f(sh.off_S2), d.S, d.plane,
+                                 g_eps, g_sig, d.NX, d.NY, d.pitch, d.dt, st) != hipSuccess)
+        rc = FWI_EHIP;
+    if (timing) {
+        double sum[K_NKINDS] = {0, 0, 0}, upd[K_NKINDS] = {0, 0, 0};
+        int cnt[K_NKINDS] = {0, 0, 0}, nl[K_NKINDS] = {0, 0, 0};
+        for (int g = 0; g < G; ++g) {
+            if (!gs[g]) continue;
+            const int rt = tm[g].collect(sum, cnt);
+            if (rc == FWI_OK) rc = rt;
+            for (int k = 0; k < K_NKINDS; ++k) {
+                nl[k] += tm[g].launches[k];
+                upd[k] += tm[g].updates[k];
+            }
+        }
+        Timer::report(timing, nl, upd, sum, cnt);
+        timing->shot_groups = G;
+    }
+    for (int g = 0; g < G; ++g)
+        if (gs[g]) {
+            if (hipStreamSynchronize(gs[g]) != hipSuccess && rc == FWI_OK) rc = FWI_EHIP;
+            (void)hipStreamDestroy(gs[g]);
+        }
+    for (int e = 0; e <= G; ++e)
+        if (ev[e]) (void)hipEventDestroy(ev[e]);
+    if (rc != FWI_OK) return rc;
+    const size_t cells = (size_t)d.NX * d.NY;
+    return check_finite(PS, g_eps, cells, g_sig, cells, misfit, st);
 }
 
 int prepare(const fwi_grid *grid, const fwi_geom *geom, int mode, void *ws,
@@ -658,6 +889,7 @@ extern "C" int fwi_workspace_bytes(const fwi_grid *grid, const fwi_geom *geom,
     Dims d;
     int rc = make_dims(grid, geom, d);
     if (rc != FWI_OK) return rc;
+    if (save_mode == -1) return gradient_workspace(d, *bytes);
     Layout L;
     rc = make_layout(d, save_mode, L);
     if (rc != FWI_OK) return rc;
@@ -718,19 +950,32 @@ extern "C" int fdtd_adjoint(const fwi_grid *grid, const fwi_geom *geom,
     return check_finite(P, grad_eps_r, cells, grad_sigma, cells, nullptr, st);
 }
 
-extern "C" int fwi_gradient_timed(const fwi_grid *grid, const fwi_geom *geom,
-                                  const float *eps_r, const float *sigma,
-                                  const float *observed, double *misfit,
-                                  float *grad_eps_r, float *grad_sigma,
-                                  float *traces_out, void *ws, size_t ws_bytes,
-                                  void *stream, fwi_timing *timing) {
+extern "C" int fwi_gradient_ex(const fwi_grid *grid, const fwi_geom *geom, const float *eps_r,
+                               const float *sigma, const float *observed, double *misfit,
+                               float *grad_eps_r, float *grad_sigma, float *traces_out,
+                               void *ws, size_t ws_bytes, void *stream, fwi_timing *timing,
+                               int32_t shot_groups) {
     if (!eps_r || !sigma || !observed || !misfit || !grad_eps_r || !grad_sigma)
         return FWI_EINVAL;
     if (timing && timing->sample_every < 1) return FWI_EINVAL;
-    Layout L;
-    int rc = prepare(grid, geom, -1, ws, ws_bytes, L);
+    if (shot_groups < 0 || shot_groups > kMaxShotGroups) return FWI_EINVAL;
+    Dims dd;
+    int rc = make_dims(grid, geom, dd);
     if (rc != FWI_OK) return rc;
+    const int G = shot_groups ? std::min(shot_groups, dd.S) : auto_shot_groups(dd);
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (G > 1) {
+        GroupLayout GL;
+        rc = make_group_layout(dd, G, GL);
+        if (rc != FWI_OK) return rc;
+        if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0 || ws_bytes < GL.total)
+            return FWI_ENOMEM;
+        return gradient_groups(dd, G, geom, eps_r, sigma, observed, misfit, grad_eps_r,
+                               grad_sigma, traces_out, ws, st, timing);
+    }
+    Layout L;
+    rc = prepare(grid, geom, -1, ws, ws_bytes, L);
+    if (rc != FWI_OK) return rc;
     Ptrs P{static_cast<char *>(ws), &L};
     const Dims &d = L.d;
     Timer tm;
@@ -749,10 +994,21 @@ extern "C" int fwi_gradient_timed(const fwi_grid *grid, const fwi_geom *geom,
         if (rc == FWI_OK) rc = do_adjoint(L, eps_r, sigma, grad_eps_r, grad_sigma, ws, st, tm);
     }
     const int rc2 = tm.finish();
+    if (timing) timing->shot_groups = 1;
     if (rc != FWI_OK) return rc;
     if (rc2 != FWI_OK) return rc2;
     const size_t cells = (size_t)d.NX * d.NY;
     return check_finite(P, grad_eps_r, cells, grad_sigma, cells, misfit, st);
+}
+
+extern "C" int fwi_gradient_timed(const fwi_grid *grid, const fwi_geom *geom,
+                                  const float *eps_r, const float *sigma,
+                                  const float *observed, double *misfit,
+                                  float *grad_eps_r, float *grad_sigma,
+                                  float *traces_out, void *ws, size_t ws_bytes,
+                                  void *stream, fwi_timing *timing) {
+    return fwi_gradient_ex(grid, geom, eps_r, sigma, observed, misfit, grad_eps_r, grad_sigma,
+                           traces_out, ws, ws_bytes, stream, timing, 0);
 }
 
 extern "C" int fwi_gradient(const fwi_grid *grid, const fwi_geom *geom,
@@ -760,8 +1016,8 @@ extern "C" int fwi_gradient(const fwi_grid *grid, const fwi_geom *geom,
                             const float *observed, double *misfit,
                             float *grad_eps_r, float *grad_sigma, float *traces_out,
                             void *ws, size_t ws_bytes, void *stream) {
-    return fwi_gradient_timed(grid, geom, eps_r, sigma, observed, misfit, grad_eps_r,
-                              grad_sigma, traces_out, ws, ws_bytes, stream, nullptr);
+    return fwi_gradient_ex(grid, geom, eps_r, sigma, observed, misfit, grad_eps_r, grad_sigma,
+                           traces_out, ws, ws_bytes, stream, nullptr, 0);
 }
 
 extern "C" const char *fwi_strerror(int status) {

@@ -23,8 +23,23 @@ void make_tiling(const Dims &d, Layout &L);
 // Row bands of height `rows` for both kernels (batched plans).
 void fixed_bands(Layout &L, int rows, int depth);
 // Workspace layout for a save mode (-1: fwi_gradient); k > 0 forces the
-// checkpoint interval (a multiple of the streaming depth).
-int make_layout(const Dims &d, int mode, Layout &L, int k = 0, int depth = 0);
+// checkpoint interval (a multiple of the streaming depth).  With `shared`,
+// one shot group's layout from byte `start` (see make_group_layout).
+int make_layout(const Dims &d, int mode, Layout &L, int k = 0, int depth = 0, size_t start = 0,
+                const Layout *shared = nullptr, int s0 = 0);
+
+// A gradient's shots in G groups run concurrently (fwi_host.cpp).
+constexpr int kMaxShotGroups = 4;
+struct GroupLayout {
+    int G;
+    int s0[kMaxShotGroups + 1];   // first shot of each group, then S
+    Layout shared;                // arrays shared by the groups (all S shots)
+    Layout grp[kMaxShotGroups];
+    size_t total;
+};
+int make_group_layout(const Dims &d, int G, GroupLayout &GL);
+int auto_shot_groups(const Dims &d);
+int gradient_workspace(const Dims &d, size_t &bytes);
 
 // Pointers into the workspace.
 struct Ptrs {

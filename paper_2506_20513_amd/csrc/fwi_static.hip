@@ -60,6 +60,7 @@ extern "C" int fwi_gradient_static(const fwi_grid *grid, const fwi_geom *geom,
     void *ws = nullptr;
     rc = scratch_address(&ws);
     if (rc != FWI_OK) return rc;
-    return fwi_gradient(grid, geom, eps_r, sigma, observed, misfit, grad_eps_r, grad_sigma,
-                        traces_out, ws, (size_t)FWI_STATIC_SCRATCH_BYTES, stream);
+    // one shot group: no streams or events are created
+    return fwi_gradient_ex(grid, geom, eps_r, sigma, observed, misfit, grad_eps_r, grad_sigma,
+                           traces_out, ws, (size_t)FWI_STATIC_SCRATCH_BYTES, stream, nullptr, 1);
 }

@@ -35,7 +35,8 @@ GRADIENT_WORKSPACE = -1   # fwi_workspace_bytes mode for fwi_gradient
 EXPORTED = ("fwi_workspace_bytes", "fdtd_forward", "fdtd_adjoint", "fwi_gradient",
             "fwi_gradient_timed", "fwi_checkpoint_interval", "fwi_strerror",
             "fwi_batch_workspace_bytes", "fwi_batch_plan_create", "fwi_batch_plan_run",
-            "fwi_batch_plan_info", "fwi_batch_plan_destroy", "fwi_gradient_static")
+            "fwi_batch_plan_info", "fwi_batch_plan_destroy", "fwi_gradient_static",
+            "fwi_gradient_ex")
 
 
 class FwiError(RuntimeError):
@@ -65,7 +66,7 @@ class fwi_kernel_time(ctypes.Structure):
 
 class fwi_timing(ctypes.Structure):
     _fields_ = [("sample_every", ctypes.c_int32), ("nkinds", ctypes.c_int32),
-                ("kind", fwi_kernel_time * TIMING_MAX_KINDS)]
+                ("kind", fwi_kernel_time * TIMING_MAX_KINDS), ("shot_groups", ctypes.c_int32)]
 
     def as_dict(self):
         return {self.kind[k].name.decode(): dict(launches=self.kind[k].launches,
@@ -132,6 +133,8 @@ def lib() -> ctypes.CDLL:
         L.fwi_gradient_timed.argtypes = [G, Q, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp,
                                          ctypes.POINTER(fwi_timing)]
         L.fwi_gradient_static.argtypes = [G, Q, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.fwi_gradient_ex.argtypes = [G, Q, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp,
+                                      ctypes.POINTER(fwi_timing), ctypes.c_int32]
         L.fwi_strerror.argtypes = [ctypes.c_int]
         L.fwi_strerror.restype = ctypes.c_char_p
         BP = ctypes.POINTER(fwi_batch_problem)
@@ -144,6 +147,7 @@ def lib() -> ctypes.CDLL:
         L.fwi_batch_plan_destroy.restype = None
         for name in ("fwi_workspace_bytes", "fwi_checkpoint_interval", "fdtd_forward",
                      "fdtd_adjoint", "fwi_gradient", "fwi_gradient_timed", "fwi_gradient_static",
+                     "fwi_gradient_ex",
                      "fwi_batch_workspace_bytes", "fwi_batch_plan_create", "fwi_batch_plan_run",
                      "fwi_batch_plan_info"):
             getattr(L, name).restype = ctypes.c_int
@@ -286,6 +290,22 @@ def fwi_gradient_timed(grid, geom, eps_r, sigma, observed, misfit, grad_eps_r, g
                                   ctypes.byref(timing) if timing is not None else None)
     if raise_on_error:
         _check(st, "fwi_gradient_timed")
+    return st
+
+
+def fwi_gradient_ex(grid, geom, eps_r, sigma, observed, misfit, grad_eps_r, grad_sigma,
+                    traces_out, ws, timing: fwi_timing | None = None, shot_groups: int = 0,
+                    stream=None, raise_on_error=True) -> int:
+    """fwi_gradient(_timed) with the shots in `shot_groups` concurrent groups
+    (0 = the library's choice); results identical for every group count."""
+    st = lib().fwi_gradient_ex(ctypes.byref(grid), ctypes.byref(geom.c), _ptr(eps_r),
+                               _ptr(sigma), _ptr(observed), _ptr(misfit),
+                               _ptr(grad_eps_r), _ptr(grad_sigma), _ptr(traces_out),
+                               _wsptr(ws), _nbytes(ws), _stream(stream),
+                               ctypes.byref(timing) if timing is not None else None,
+                               int(shot_groups))
+    if raise_on_error:
+        _check(st, "fwi_gradient_ex")
     return st
 
 

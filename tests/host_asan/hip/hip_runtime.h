@@ -44,6 +44,7 @@ typedef enum hipStreamCaptureMode {
 } hipStreamCaptureMode;
 
 #define hipStreamNonBlocking 0x1
+#define hipEventDisableTiming 0x2
 
 /* device-side qualifiers of a file-scope array: plain host storage here */
 #define __device__
@@ -66,6 +67,8 @@ hipError_t hipGraphLaunch(hipGraphExec_t exec, hipStream_t stream);
 hipError_t hipGraphDestroy(hipGraph_t graph);
 hipError_t hipGraphExecDestroy(hipGraphExec_t exec);
 hipError_t hipEventCreate(hipEvent_t *event);
+hipError_t hipEventCreateWithFlags(hipEvent_t *event, unsigned flags);
+hipError_t hipStreamWaitEvent(hipStream_t stream, hipEvent_t event, unsigned flags);
 hipError_t hipEventDestroy(hipEvent_t event);
 hipError_t hipEventRecord(hipEvent_t event, hipStream_t stream);
 hipError_t hipEventSynchronize(hipEvent_t event);

@@ -41,6 +41,11 @@ hipError_t hipEventCreate(hipEvent_t *e) {
     *e = new ihipEvent_t{0};
     return hipSuccess;
 }
+hipError_t hipEventCreateWithFlags(hipEvent_t *e, unsigned) {
+    *e = new ihipEvent_t{0};
+    return hipSuccess;
+}
+hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned) { return hipSuccess; }
 hipError_t hipEventDestroy(hipEvent_t e) {
     delete e;
     return hipSuccess;

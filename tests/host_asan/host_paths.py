@@ -62,6 +62,14 @@ def run_single(cfg, src, rec):
     fwi.fwi_gradient_timed(grid, geom, a["eps"], a["sig"], a["obs"], a["mis"], a["ge"],
                            a["gs"], None, ws, t, stream=0)
     assert t.as_dict()["k_adj"]["launches"] > 0
+    # shots in concurrent groups: the group layouts inside the same workspace
+    for G in (2, 3, 4):
+        if G <= src.shape[0]:
+            t = fwi.fwi_timing(sample_every=2)
+            fwi.fwi_gradient_ex(grid, geom, a["eps"], a["sig"], a["obs"], a["mis"], a["ge"],
+                                a["gs"], a["tr"] if G != 3 else None, ws, timing=t,
+                                shot_groups=G, stream=0)
+            assert t.as_dict()["k_adj"]["launches"] > 0
     for mode in (fwi.FWI_SAVE_NONE, fwi.FWI_SAVE_CHECKPOINT, fwi.FWI_SAVE_HISTORY):
         nb = fwi.workspace_bytes(grid, geom, mode)
         ws = (buf(nb), nb)
