@@ -18,8 +18,9 @@ int make_dims(const fwi_grid *grid, const fwi_geom *geom, Dims &d);
 // Checkpoint interval minimising checkpoint plus segment-buffer memory.
 int stream_depth(const Dims &d);
 int choose_k(const Dims &d, int depth);
-// Row bands of the streaming decomposition (stored in L).
-void make_tiling(const Dims &d, Layout &L);
+// Row bands of the streaming decomposition (stored in L); `groups` shot
+// groups share the chip.
+void make_tiling(const Dims &d, Layout &L, int groups = 1);
 // Row bands of height `rows` for both kernels (batched plans).
 void fixed_bands(Layout &L, int rows, int depth);
 // Workspace layout for a save mode (-1: fwi_gradient); k > 0 forces the
