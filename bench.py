@@ -183,7 +183,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="uneven workload: default bands")
     ap.add_argument("--sequential", action="store_true",
                     help="uneven workload: also time the problems one by one")
-    ap.add_argument("--sample-every", type=int, default=8,
+    ap.add_argument("--sample-every", type=int, default=32,
                     help="time every k-th launch of each hot kernel with HIP events")
     ap.add_argument("--nt", type=int, default=None,
                     help="override the number of time steps (short profiler runs)")

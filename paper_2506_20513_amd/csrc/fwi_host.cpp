@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 namespace fwi {
@@ -820,10 +821,30 @@ int gradient_groups(const Dims &d, int G, const fwi_geom *geom, const float *eps
         }
         return r;
     };
+    // Each group's launches are issued from a host thread of its own, so
+    // that every group starts at once: issued from one thread, the last
+    // group would wait for the others' thousands of launches to be issued.
+    // The threads make the caller's current device theirs before they
+    // issue anything.
+    int dev = 0;
+    if (rc == FWI_OK && hipGetDevice(&dev) != hipSuccess) rc = FWI_EHIP;
+    auto each_group = [&](auto &&phase) -> int {
+        int rcs[kMaxShotGroups] = {FWI_OK, FWI_OK, FWI_OK, FWI_OK};
+        std::vector<std::thread> th;
+        for (int g = 1; g < G; ++g)
+            th.emplace_back([&, g] {
+                rcs[g] = hipSetDevice(dev) == hipSuccess ? phase(g) : FWI_EHIP;
+            });
+        rcs[0] = phase(0);
+        for (auto &t : th) t.join();
+        for (int g = 0; g < G; ++g)
+            if (rcs[g] != FWI_OK) return rcs[g];
+        return FWI_OK;
+    };
     if (rc == FWI_OK) {
         rc = fork();
-        for (int g = 0; g < G && rc == FWI_OK; ++g)
-            rc = forward_run(GL.grp[g], ws, true, gs[g], tm[g]);
+        if (rc == FWI_OK)
+            rc = each_group([&](int g) { return forward_run(GL.grp[g], ws, true, gs[g], tm[g]); });
         const int rj = join();
         if (rc == FWI_OK) rc = rj;
     }
@@ -834,8 +855,11 @@ int gradient_groups(const Dims &d, int G, const fwi_geom *geom, const float *eps
         rc = FWI_EHIP;
     if (rc == FWI_OK) {
         rc = fork();
-        for (int g = 0; g < G && rc == FWI_OK; ++g)
-            rc = do_adjoint(GL.grp[g], eps_r, sigma, nullptr, nullptr, ws, gs[g], tm[g], false);
+        if (rc == FWI_OK)
+            rc = each_group([&](int g) {
+                return do_adjoint(GL.grp[g], eps_r, sigma, nullptr, nullptr, ws, gs[g], tm[g],
+                                  false);
+            });
         const int rj = join();
         if (rc == FWI_OK) rc = rj;
     }

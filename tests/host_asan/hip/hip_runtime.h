@@ -52,6 +52,7 @@ typedef enum hipStreamCaptureMode {
 #define HIP_SYMBOL(x) (&(x))
 
 hipError_t hipGetDevice(int *device);
+hipError_t hipSetDevice(int device);
 hipError_t hipGetSymbolAddress(void **ptr, const void *symbol);
 
 hipError_t hipMemcpyAsync(void *dst, const void *src, size_t bytes, hipMemcpyKind kind,

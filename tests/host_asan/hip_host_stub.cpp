@@ -57,6 +57,7 @@ hipError_t hipEventElapsedTime(float *ms, hipEvent_t, hipEvent_t) {
     return hipSuccess;
 }
 hipError_t hipGetLastError(void) { return hipSuccess; }
+hipError_t hipSetDevice(int) { return hipSuccess; }
 hipError_t hipGetDevice(int *device) {
     *device = 0;
     return hipSuccess;

@@ -54,7 +54,7 @@ def _clean(p):
 @pytest.fixture(scope="module")
 def host_lib(tmp_path_factory):
     so = str(tmp_path_factory.mktemp("asan") / "libfwi_host_asan.so")
-    cmd = ["g++", "-std=c++17", "-fPIC", "-shared", "-Wall", "-Wno-unused-function", *SAN,
+    cmd = ["g++", "-std=c++17", "-fPIC", "-shared", "-pthread", "-Wall", "-Wno-unused-function", *SAN,
            "-I", os.path.join(ROOT, "tests", "host_asan"), "-I", os.path.join(ROOT, "include"),
            "-I", CSRC, os.path.join(ROOT, "tests", "host_asan", "hip_host_stub.cpp"),
            os.path.join(CSRC, "fwi_host.cpp"), os.path.join(CSRC, "fwi_batch.cpp"),
