@@ -828,14 +828,24 @@ int gradient_groups(const Dims &d, int G, const fwi_geom *geom, const float *eps
     // issue anything.
     int dev = 0;
     if (rc == FWI_OK && hipGetDevice(&dev) != hipSuccess) rc = FWI_EHIP;
+    // A group whose thread cannot be started is issued from this thread
+    // after the others (no exception leaves the C ABI).
     auto each_group = [&](auto &&phase) -> int {
         int rcs[kMaxShotGroups] = {FWI_OK, FWI_OK, FWI_OK, FWI_OK};
+        bool threaded[kMaxShotGroups] = {false, false, false, false};
         std::vector<std::thread> th;
-        for (int g = 1; g < G; ++g)
-            th.emplace_back([&, g] {
-                rcs[g] = hipSetDevice(dev) == hipSuccess ? phase(g) : FWI_EHIP;
-            });
+        for (int g = 1; g < G; ++g) {
+            try {
+                th.emplace_back([&, g] {
+                    rcs[g] = hipSetDevice(dev) == hipSuccess ? phase(g) : FWI_EHIP;
+                });
+                threaded[g] = true;
+            } catch (...) {
+            }
+        }
         rcs[0] = phase(0);
+        for (int g = 1; g < G; ++g)
+            if (!threaded[g]) rcs[g] = phase(g);
         for (auto &t : th) t.join();
         for (int g = 0; g < G; ++g)
             if (rcs[g] != FWI_OK) return rcs[g];
