@@ -301,6 +301,13 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
     # mean number of stencil launches running at once over the timed steps
     in_flight = sum(k["ms_per_step"] for k in kernels.values()) / ms_per_step
+    # measured HBM traffic of all stencil launches of a step over the step
+    # time (null unless every kind has a counter figure)
+    step_traffic = None
+    if all(k["traffic_bytes_per_launch"] for k in kernels.values()):
+        step_traffic = sum(k["traffic_bytes_per_launch"] * k["launches_per_step"]
+                           for k in kernels.values())
+    step_gbps = step_traffic / (ms_per_step / 1e3) / 1e9 if step_traffic else None
     by = kernels[dom]["bytes_per_launch"]
     achieved = kernels[dom]["algorithmic_GBps"]
     traffic = kernels[dom]["traffic_bytes_per_launch"]
@@ -336,6 +343,8 @@ def main():
                      "measured_frac": round(measured / HBM_PEAK_GBS, 4) if measured else None,
                      "shot_groups": groups,
                      "launches_in_flight": round(in_flight, 3),
+                     "step_measured_GBps": round(step_gbps, 1) if step_gbps else None,
+                     "step_measured_frac": round(step_gbps / HBM_PEAK_GBS, 4) if step_gbps else None,
                      "note": "achieved counts the algorithmic bytes of one HBM sweep per time "
                              "step; one launch advances several steps per sweep (temporal "
                              "blocking), so frac can exceed 1. measured_frac divides the "
@@ -344,7 +353,8 @@ def main():
                              "streams; each launch covers one group, and its duration includes "
                              "the other groups' launches running beside it (launches_in_flight "
                              "on average), so per-launch rates are a share of the GPU's; "
-                             "effective_hbm_frac is the whole step's algorithmic rate."},
+                             "effective_hbm_frac is the whole step's algorithmic rate and "
+                             "step_measured_frac its measured HBM traffic over the step."},
         "kernels": kernels,
         "misfit": float(mis.item()),
     }
