@@ -90,6 +90,29 @@ def test_large_grid_automatic_groups_bitwise_and_timing():
     assert _same(_run(cfg, grid, geom, e0, s0, obs, ws2, 2), ref)
 
 
+def test_groups_on_a_side_stream_without_traces_out():
+    """The grouped call on a non-default caller stream, with the traces kept
+    in the workspace, twice in a row on the same workspace: the same
+    results as one group on the default stream."""
+    import torch
+    cfg = I.config_survey().with_(nt=160)
+    grid, geom, e0, s0, obs = _problem(cfg)
+    ws = fwi.alloc_workspace(fwi.workspace_bytes(grid, geom, fwi.GRADIENT_WORKSPACE))
+    ref = _run(cfg, grid, geom, e0, s0, obs, ws, 1)
+    side = torch.cuda.Stream()
+    for _ in range(2):
+        mis = torch.full((1,), float("nan"), dtype=torch.float64, device="cuda")
+        ge = torch.full((cfg.NY, cfg.NX), float("nan"), device="cuda")
+        gs = torch.full_like(ge, float("nan"))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            fwi.fwi_gradient_ex(grid, geom, e0, s0, obs, mis, ge, gs, None, ws, shot_groups=3,
+                                stream=side)
+        side.synchronize()
+        assert torch.equal(mis.cpu(), ref[0])
+        assert torch.equal(ge.cpu(), ref[1]) and torch.equal(gs.cpu(), ref[2])
+
+
 def test_group_count_checks():
     import torch
     cfg = I.config_tiny().with_(nt=20)
