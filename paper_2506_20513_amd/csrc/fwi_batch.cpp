@@ -28,7 +28,7 @@ namespace batch {
 
 using namespace host;
 
-enum OpKind { OP_FWD = 0, OP_ADJ = 1, OP_CALL = 2 };
+enum OpKind { OP_FWD = 0, OP_ADJ = 1, OP_CALL = 2, OP_COPY = 3 };
 
 // Schedule position: (phase, a, b, c), compared lexicographically.
 struct Key {
@@ -50,15 +50,19 @@ struct Op {
     FwdStreamArgs fa;
     AdjStreamArgs aa;
     std::function<hipError_t(hipStream_t)> fn;
+    std::vector<CopyEntry> cp;     // OP_COPY: device-to-device copies
 };
 
-// One executable step of the plan.
+// One executable step of the plan.  A copy step copies the entries of every
+// problem's OP_COPY at one schedule position in one launch (table at
+// tab_off, prefix sums at boff_off, ctotal floats in all).
 struct Step {
     OpKind kind;
     bool tail;
     int depth;                     // temporal depth of a stencil step
     int nm;
     unsigned nblocks;
+    unsigned long long ctotal;     // copy steps: floats copied
     size_t tab_off, boff_off;      // byte offsets in the workspace
     std::function<hipError_t(hipStream_t)> fn;
 };
@@ -98,6 +102,24 @@ void record(int ip, Problem &p, char *ws, std::vector<Op> &ops) {
         o.fn = std::move(fn);
         ops.push_back(std::move(o));
     };
+    // E and the full state (H, CPML memories) from (esrc, ssrc) to (edst,
+    // sdst), as copy_state and one E copy would do
+    auto copies = [&](Key k, float *edst, const float *esrc, const State &sdst,
+                      const State &ssrc) {
+        const unsigned long long S = (unsigned long long)d.S, f = S * d.plane;
+        Op o;
+        o.key = k;
+        o.kind = OP_COPY;
+        o.prob = ip;
+        o.cp = {{edst, esrc, f},
+                {sdst.Hx, ssrc.Hx, f},
+                {sdst.Hy, ssrc.Hy, f},
+                {sdst.phx, ssrc.phx, S * d.ys},
+                {sdst.phy, ssrc.phy, S * d.xs},
+                {sdst.pex, ssrc.pex, S * d.xs},
+                {sdst.pey, ssrc.pey, S * d.ys}};
+        ops.push_back(std::move(o));
+    };
     const size_t field = (size_t)d.S * d.plane;
     const size_t fbytes = field * sizeof(float);
     const int D = L.depth;
@@ -121,14 +143,9 @@ void record(int ip, Problem &p, char *ws, std::vector<Op> &ops) {
     for (int n0 = 0; n0 < d.nt; n0 += L.K) {
         const int n1 = std::min(d.nt, n0 + L.K);
         const int c = n0 / L.K;
-        char *cp = ws + p.base + L.off_ckpt + (size_t)c * L.ckpt_stride;
+        float *cp = P.f(L.off_ckpt + (size_t)c * L.ckpt_stride);
         const State cst = P.state(L.off_ckpt + (size_t)c * L.ckpt_stride + align_up(fbytes), false);
-        const float *esrc = P.slot(e);
-        const State fsrc = fs[cur];
-        call({{1, n0, 0, 0}}, [=](hipStream_t st) {
-            hipError_t r = hipMemcpyAsync(cp, esrc, fbytes, hipMemcpyDeviceToDevice, st);
-            return r == hipSuccess ? ok(copy_state(cst, fsrc, d, st)) : r;
-        });
+        copies({{1, n0, 0, 0}}, cp, P.slot(e), cst, fs[cur]);
         for (int n = n0; n < n1; n += D) {
             a.n = n;
             a.nlev = std::min(D, n1 - n);
@@ -173,13 +190,9 @@ void record(int ip, Problem &p, char *ws, std::vector<Op> &ops) {
     for (int c = L.ncp - 1; c >= 0; --c) {
         const int n0 = c * L.K, n1 = std::min(d.nt, n0 + L.K);
         const int X = kSegBase - c;
-        const char *cp = ws + p.base + L.off_ckpt + (size_t)c * L.ckpt_stride;
+        const float *cp = P.f(L.off_ckpt + (size_t)c * L.ckpt_stride);
         const State cst = P.state(L.off_ckpt + (size_t)c * L.ckpt_stride + align_up(fbytes), false);
-        float *slot0 = P.slot(0);
-        call({{4, X, 0, 0}}, [=](hipStream_t st) {
-            hipError_t r = hipMemcpyAsync(slot0, cp, fbytes, hipMemcpyDeviceToDevice, st);
-            return r == hipSuccess ? ok(copy_state(fs[0], cst, d, st)) : r;
-        });
+        copies({{4, X, 0, 0}}, P.slot(0), cp, fs[0], cst);
         int fcur = 0, j = 0;
         FwdStreamArgs f = fwd_args(P);
         f.record = 0;
@@ -240,33 +253,44 @@ struct Schedule {
     std::vector<FwdStreamArgs> ftab;
     std::vector<AdjStreamArgs> atab;
     std::vector<unsigned> boff;
-    size_t f_off = 0, a_off = 0, b_off = 0, bytes = 0;
+    std::vector<CopyEntry> ctab;
+    std::vector<unsigned long long> ccum;
+    size_t f_off = 0, a_off = 0, b_off = 0, c_off = 0, cc_off = 0, bytes = 0;
     int stencil_launches = 0;
 };
 
-size_t area_bytes(size_t nf, size_t na, size_t nb) {
+size_t area_bytes(size_t nf, size_t na, size_t nb, size_t nc, size_t ncc) {
     return align_up(nf * sizeof(FwdStreamArgs)) + align_up(na * sizeof(AdjStreamArgs)) +
-           align_up(nb * sizeof(unsigned));
+           align_up(nb * sizeof(unsigned)) + align_up(nc * sizeof(CopyEntry)) +
+           align_up(ncc * sizeof(unsigned long long));
 }
 
 void build_schedule(std::vector<Problem> &probs, char *ws, size_t area, Schedule &S) {
     std::vector<Op> ops;
     for (int i = 0; i < (int)probs.size(); ++i) record(i, probs[i], ws, ops);
     std::stable_sort(ops.begin(), ops.end(), [](const Op &x, const Op &y) { return x.key < y.key; });
-    size_t nf = 0, na = 0, nb = 0;
+    size_t nf = 0, na = 0, nb = 0, nc = 0, ncc = 0;
     for (const Op &o : ops) {
         if (o.kind == OP_FWD) ++nf;
         if (o.kind == OP_ADJ) ++na;
+        if (o.kind == OP_COPY) {
+            nc += o.cp.size();
+            ncc += o.cp.size() + 1;   // upper bound: one extra sum per step
+        }
     }
     nb = nf + na + 2 * ops.size();    // upper bound: one extra offset per group
     S.f_off = area;
     S.a_off = S.f_off + align_up(nf * sizeof(FwdStreamArgs));
     S.b_off = S.a_off + align_up(na * sizeof(AdjStreamArgs));
-    S.bytes = area_bytes(nf, na, nb);
+    S.c_off = S.b_off + align_up(nb * sizeof(unsigned));
+    S.cc_off = S.c_off + align_up(nc * sizeof(CopyEntry));
+    S.bytes = area_bytes(nf, na, nb, nc, ncc);
     S.steps.clear();
     S.ftab.clear();
     S.atab.clear();
     S.boff.clear();
+    S.ctab.clear();
+    S.ccum.clear();
     S.stencil_launches = 0;
     for (size_t i = 0; i < ops.size();) {
         const Op &o = ops[i];
@@ -277,10 +301,35 @@ void build_schedule(std::vector<Problem> &probs, char *ws, size_t area, Schedule
             s.depth = 0;
             s.nm = 0;
             s.nblocks = 0;
+            s.ctotal = 0;
             s.tab_off = s.boff_off = 0;
             s.fn = o.fn;
             S.steps.push_back(std::move(s));
             ++i;
+            continue;
+        }
+        if (o.kind == OP_COPY) {
+            // every problem's copies at this position in one launch
+            Step s;
+            s.kind = OP_COPY;
+            s.tail = false;
+            s.depth = 0;
+            s.nm = 0;
+            s.nblocks = 0;
+            s.ctotal = 0;
+            s.tab_off = S.c_off + S.ctab.size() * sizeof(CopyEntry);
+            s.boff_off = S.cc_off + S.ccum.size() * sizeof(unsigned long long);
+            size_t j = i;
+            for (; j < ops.size() && ops[j].kind == OP_COPY && ops[j].key == o.key; ++j)
+                for (const CopyEntry &c : ops[j].cp) {
+                    S.ccum.push_back(s.ctotal);
+                    S.ctab.push_back(c);
+                    s.ctotal += c.n;
+                    ++s.nm;
+                }
+            S.ccum.push_back(s.ctotal);
+            S.steps.push_back(std::move(s));
+            i = j;
             continue;
         }
         size_t j = i;
@@ -294,6 +343,7 @@ void build_schedule(std::vector<Problem> &probs, char *ws, size_t area, Schedule
             s.depth = depth;
             s.nm = 0;
             s.nblocks = 0;
+            s.ctotal = 0;
             s.boff_off = S.b_off + S.boff.size() * sizeof(unsigned);
             s.tab_off = o.kind == OP_FWD ? S.f_off + S.ftab.size() * sizeof(FwdStreamArgs)
                                          : S.a_off + S.atab.size() * sizeof(AdjStreamArgs);
@@ -322,6 +372,10 @@ void build_schedule(std::vector<Problem> &probs, char *ws, size_t area, Schedule
 
 hipError_t run_step(const Step &s, char *ws, hipStream_t st) {
     if (s.kind == OP_CALL) return s.fn(st);
+    if (s.kind == OP_COPY)
+        return launch_copy_table(reinterpret_cast<const CopyEntry *>(ws + s.tab_off),
+                                 reinterpret_cast<const unsigned long long *>(ws + s.boff_off),
+                                 s.nm, s.ctotal, st);
     const unsigned *boff = reinterpret_cast<const unsigned *>(ws + s.boff_off);
     if (s.kind == OP_FWD)
         return launch_fwd_table(reinterpret_cast<const FwdStreamArgs *>(ws + s.tab_off), boff,
@@ -340,6 +394,13 @@ int upload_tables(const Schedule &S, char *ws, hipStream_t st) {
     if (!S.boff.empty())
         FWI_TRY(hipMemcpyAsync(ws + S.b_off, S.boff.data(), S.boff.size() * sizeof(unsigned),
                                hipMemcpyHostToDevice, st));
+    if (!S.ctab.empty())
+        FWI_TRY(hipMemcpyAsync(ws + S.c_off, S.ctab.data(), S.ctab.size() * sizeof(CopyEntry),
+                               hipMemcpyHostToDevice, st));
+    if (!S.ccum.empty())
+        FWI_TRY(hipMemcpyAsync(ws + S.cc_off, S.ccum.data(),
+                               S.ccum.size() * sizeof(unsigned long long), hipMemcpyHostToDevice,
+                               st));
     FWI_TRY(hipStreamSynchronize(st));
     return FWI_OK;
 }
@@ -519,7 +580,8 @@ extern "C" int fwi_batch_plan_create(int32_t n, const fwi_batch_problem *problem
                 if (rc != FWI_OK) break;
                 // run the set-up steps once so the first pass reads valid state
                 size_t first = 0;
-                while (first < S.steps.size() && S.steps[first].kind == OP_CALL) {
+                while (first < S.steps.size() &&
+                       (S.steps[first].kind == OP_CALL || S.steps[first].kind == OP_COPY)) {
                     if (run_step(S.steps[first], w, st) != hipSuccess) rc = FWI_EHIP;
                     ++first;
                 }

@@ -169,6 +169,19 @@ hipError_t launch_coefficients(const float *eps_r, const float *sigma, float *Ca
                                hipStream_t st);
 hipError_t launch_profiles(const Dims &d, const Profiles &p, hipStream_t st);
 hipError_t launch_fill(float *dst, size_t n, float v, hipStream_t st);
+// One device-to-device copy of n floats; the batched plans merge the
+// checkpoint copies of every problem at one schedule position into one
+// launch over a table of these.
+struct CopyEntry {
+    float *dst;
+    const float *src;
+    unsigned long long n;
+};
+// Copies every entry of tab (device, nent entries); cum (device, nent + 1
+// values) holds the prefix sums of the entries' n, cum[nent] = total.  The
+// entries must not overlap one another.
+hipError_t launch_copy_table(const CopyEntry *tab, const unsigned long long *cum, int nent,
+                             unsigned long long total, hipStream_t st);
 hipError_t launch_gradient_finalize(const float *eps_r, const float *sigma,
                                     const float *S1, const float *S2, int S,
                                     size_t plane, float *g_eps, float *g_sig, int NX,

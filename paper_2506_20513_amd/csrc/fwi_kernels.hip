@@ -94,6 +94,34 @@ __global__ void k_fill(float *__restrict__ dst, size_t n, float v) {
         dst[t] = v;
 }
 
+// Merged copies: block b copies floats [b C, (b + 1) C) of the entries laid
+// end to end, starting from the entry its first float falls in (binary
+// search over the prefix sums) and moving on to the next entries.
+constexpr unsigned long long kCopyChunk = 8192;
+
+__global__ __launch_bounds__(256) void k_copy_table(const CopyEntry *__restrict__ tab,
+                                                    const unsigned long long *__restrict__ cum,
+                                                    int nent, unsigned long long total) {
+    const unsigned long long beg = (unsigned long long)blockIdx.x * kCopyChunk;
+    const unsigned long long end = beg + kCopyChunk < total ? beg + kCopyChunk : total;
+    int lo = 0, hi = nent - 1;            // the last entry with cum[e] <= beg
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (cum[mid] <= beg)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    for (int e = lo; e < nent && cum[e] < end; ++e) {
+        const unsigned long long c0 = cum[e];
+        const unsigned long long a = beg > c0 ? beg : c0;
+        const unsigned long long b = end < cum[e + 1] ? end : cum[e + 1];
+        float *dst = tab[e].dst;
+        const float *src = tab[e].src;
+        for (unsigned long long i = a + threadIdx.x; i < b; i += blockDim.x) dst[i - c0] = src[i - c0];
+    }
+}
+
 // Shot sums of the correlations, in shot order and double precision, then
 // g_eps = -eps0/(dt EA) S1, g_sig = -S2/(2 EA) on updated, non-PEC cells.
 __global__ void k_gradient_finalize(const float *__restrict__ eps_r,
@@ -233,6 +261,16 @@ hipError_t launch_fill(float *dst, size_t n, float v, hipStream_t st) {
     size_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, dst, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_table(const CopyEntry *tab, const unsigned long long *cum, int nent,
+                             unsigned long long total, hipStream_t st) {
+    if (total == 0 || nent < 1) return hipSuccess;
+    const unsigned long long blocks = (total + kCopyChunk - 1) / kCopyChunk;
+    if (blocks > 0x7fffffffull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_copy_table, dim3((unsigned)blocks), dim3(256), 0, st, tab, cum, nent,
+                       total);
     return hipGetLastError();
 }
 
