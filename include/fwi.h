@@ -56,8 +56,9 @@
  *   library (see there).
  * - Every call runs on `stream` (a hipStream_t; NULL = the null stream).
  *   A gradient call that splits its shots into groups (fwi_gradient_ex)
- *   also creates one non-blocking stream per group and a few events, joins
- *   them to `stream` and destroys them before it returns.
+ *   also creates a non-blocking stream for every group but the first (which
+ *   runs on `stream`) and a few events, joins them to `stream` and destroys
+ *   them before it returns.
  *   Host arrays may be reused as soon as the call returns.  The forward,
  *   adjoint and gradient calls return once the stream has finished them
  *   (see Errors); the batched runs are asynchronous, and their device
@@ -224,11 +225,12 @@ int fwi_gradient_timed(const fwi_grid *grid, const fwi_geom *geom,
  * gradient (a sum over all shots in shot order) run on `stream` between
  * the groups' phases, so the results are identical bit for bit for every
  * group count.  shot_groups: 0 = automatic (with 16 or more shots one group
- * per 8 shots, at most 3: the 64-shot 2088 x 1064 gradient measured 11%
- * faster in 2 or 3 groups than in one, the 24-shot 552 x 296 one 6% faster
- * in 3; 1 group below 16 shots), 1 .. 4 = that many (at most nshots; 4
- * groups were slower than 3 under the runtime's default of four hardware
- * queues per process).  fwi_workspace_bytes(..., -1, ...) covers every
+ * per 6 shots, at most 4: the 64-shot 2088 x 1064 gradient measured 14%
+ * faster in 4 groups than in one, the 24-shot 552 x 296 one 16% faster;
+ * 1 group below 16 shots), 1 .. 4 = that many (at most nshots).  Group 0
+ * runs on `stream`, the others on streams the call creates, so four groups
+ * fit the runtime's default of four hardware queues per process.
+ * fwi_workspace_bytes(..., -1, ...) covers every
  * group count.  With timing, each kind's launches of all groups are
  * counted and timed; their durations include the other groups' launches
  * running beside them.  FWI_EINVAL if shot_groups is outside 0 .. 4.

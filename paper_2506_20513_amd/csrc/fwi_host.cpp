@@ -305,16 +305,17 @@ int make_group_layout(const Dims &d, int G, GroupLayout &GL) {
     return FWI_OK;
 }
 
-// Shot groups of a gradient call: with 16 or more shots, one group per 8
-// shots up to three; one group otherwise.  The groups' launches fill each
+// Shot groups of a gradient call: with 16 or more shots, one group per 6
+// shots up to four; one group otherwise.  The groups' launches fill each
 // other's last, partial rounds of waves and hide each other's pipeline
-// starts.  Measured (one group -> two -> three -> four): 2088 x 1064 cells,
-// 64 shots: 5.60 -> 4.97 -> 4.96 -> 5.63 s; 552 x 296 cells, 24 shots:
-// 0.175 -> 0.177 -> 0.164 -> 0.225 s.  Four group streams exceed the four
-// hardware queues a process gets by default, so two groups share a queue
-// and run one after the other.
+// starts.  Group 0 runs on the caller's stream, so four groups use four
+// streams, as many as the hardware queues a process gets by default (with
+// every group on a new stream, the fifth stream made four groups slower than
+// three).  Measured (one group -> two -> three -> four): 2088 x 1064 cells,
+// 64 shots: 5.60 -> 4.97 -> 4.87 -> 4.80 s; 552 x 296 cells, 24 shots:
+// 0.175 -> 0.177 -> 0.149 -> 0.147 s.
 int auto_shot_groups(const Dims &d) {
-    return d.S >= 16 ? std::min(3, d.S / 8) : 1;
+    return d.S >= 16 ? std::min(kMaxShotGroups, d.S / 6) : 1;
 }
 
 // Gradient workspace: enough for one group and for every group count up to
@@ -794,11 +795,20 @@ int gradient_groups(const Dims &d, int G, const fwi_geom *geom, const float *eps
         rc = upload_geometry(P, &gg[g], cold, st);
         if (rc != FWI_OK) return rc;
     }
+    // group 0 runs on the caller's stream, every other group on a stream of
+    // its own: G streams in all, which the runtime's default of four
+    // hardware queues per process serves side by side up to four groups
     hipStream_t gs[kMaxShotGroups] = {};
+    bool made[kMaxShotGroups] = {false, false, false, false};
     hipEvent_t ev[kMaxShotGroups + 1] = {};
     Timer tm[kMaxShotGroups];
-    for (int g = 0; g < G && rc == FWI_OK; ++g)
-        if (hipStreamCreateWithFlags(&gs[g], hipStreamNonBlocking) != hipSuccess) rc = FWI_EHIP;
+    gs[0] = st;
+    for (int g = 1; g < G && rc == FWI_OK; ++g) {
+        if (hipStreamCreateWithFlags(&gs[g], hipStreamNonBlocking) != hipSuccess)
+            rc = FWI_EHIP;
+        else
+            made[g] = true;
+    }
     for (int e = 0; e <= G && rc == FWI_OK; ++e)
         if (hipEventCreateWithFlags(&ev[e], hipEventDisableTiming) != hipSuccess) rc = FWI_EHIP;
     for (int g = 0; g < G; ++g) {
@@ -807,14 +817,14 @@ int gradient_groups(const Dims &d, int G, const fwi_geom *geom, const float *eps
     }
     auto fork = [&]() -> int {
         FWI_TRY(hipEventRecord(ev[G], st));
-        for (int g = 0; g < G; ++g) FWI_TRY(hipStreamWaitEvent(gs[g], ev[G], 0));
+        for (int g = 1; g < G; ++g) FWI_TRY(hipStreamWaitEvent(gs[g], ev[G], 0));
         return FWI_OK;
     };
-    // joins every group stream, also after a failed step
+    // joins every group stream to the caller's, also after a failed step
     auto join = [&]() -> int {
         int r = FWI_OK;
-        for (int g = 0; g < G; ++g) {
-            if (!gs[g] || !ev[g]) continue;
+        for (int g = 1; g < G; ++g) {
+            if (!made[g] || !ev[g]) continue;
             if (hipEventRecord(ev[g], gs[g]) != hipSuccess ||
                 hipStreamWaitEvent(st, ev[g], 0) != hipSuccess)
                 r = FWI_EHIP;
@@ -881,7 +891,7 @@ int gradient_groups(const Dims &d, int G, const fwi_geom *geom, const float *eps
         double sum[K_NKINDS] = {0, 0, 0}, upd[K_NKINDS] = {0, 0, 0};
         int cnt[K_NKINDS] = {0, 0, 0}, nl[K_NKINDS] = {0, 0, 0};
         for (int g = 0; g < G; ++g) {
-            if (!gs[g]) continue;
+            if (g > 0 && !made[g]) continue;
             const int rt = tm[g].collect(sum, cnt);
             if (rc == FWI_OK) rc = rt;
             for (int k = 0; k < K_NKINDS; ++k) {
@@ -892,8 +902,8 @@ int gradient_groups(const Dims &d, int G, const fwi_geom *geom, const float *eps
         Timer::report(timing, nl, upd, sum, cnt);
         timing->shot_groups = G;
     }
-    for (int g = 0; g < G; ++g)
-        if (gs[g]) {
+    for (int g = 1; g < G; ++g)
+        if (made[g]) {
             if (hipStreamSynchronize(gs[g]) != hipSuccess && rc == FWI_OK) rc = FWI_EHIP;
             (void)hipStreamDestroy(gs[g]);
         }

@@ -70,9 +70,9 @@ def test_survey_grid_every_group_count_bitwise():
 
 def test_large_grid_automatic_groups_bitwise_and_timing():
     """2088 x 1064 cells, 64 shots, a short window: the automatic choice is
-    three groups; results as with one group, and the timing of both counts
-    the same cell-updates (the three-group call makes three times the
-    launches, each over a third of the shots)."""
+    four groups; results as with one group, and the timing of both counts
+    the same cell-updates (the four-group call makes four times the
+    launches, each over a quarter of the shots)."""
     cfg = I.config_large().with_(nt=48)
     grid, geom, e0, s0, obs = _problem(cfg)
     ws = fwi.alloc_workspace(fwi.workspace_bytes(grid, geom, fwi.GRADIENT_WORKSPACE))
@@ -81,13 +81,13 @@ def test_large_grid_automatic_groups_bitwise_and_timing():
     got = _run(cfg, grid, geom, e0, s0, obs, ws, 0, t0)
     assert _same(got, ref)
     d1, d0 = t1.as_dict(), t0.as_dict()
-    assert t1.shot_groups == 1 and t0.shot_groups == 3
+    assert t1.shot_groups == 1 and t0.shot_groups == 4
     for k in ("k_fwd_sweep", "k_fwd_reforward", "k_adj"):
-        assert d0[k]["launches"] == 3 * d1[k]["launches"], (k, d0[k], d1[k])
+        assert d0[k]["launches"] == 4 * d1[k]["launches"], (k, d0[k], d1[k])
         assert d0[k]["cell_updates"] == d1[k]["cell_updates"], k
         assert d0[k]["timed"] == d0[k]["launches"] and d0[k]["avg_ms"] > 0, k
     ws2 = fwi.alloc_workspace(fwi.workspace_bytes(grid, geom, fwi.GRADIENT_WORKSPACE))
-    assert _same(_run(cfg, grid, geom, e0, s0, obs, ws2, 2), ref)
+    assert _same(_run(cfg, grid, geom, e0, s0, obs, ws2, 3), ref)
 
 
 def test_groups_on_a_side_stream_without_traces_out():
