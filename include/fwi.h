@@ -314,8 +314,10 @@ typedef struct fwi_batch_info {
     int32_t tune_depth[FWI_BATCH_MAX_TUNE]; /* each candidate's depth         */
     int32_t tune_rows[FWI_BATCH_MAX_TUNE];  /* and band height (0: default)   */
     double tune_ms[FWI_BATCH_MAX_TUNE];     /* its cost per time step, ms:
-                                  (2 x first merged forward pass + first
-                                  merged adjoint pass) / depth, best of 3   */
+                                  (forward sweep + segment re-forward +
+                                  adjoint pass) / depth, each the largest
+                                  merged full-depth launch of its kind,
+                                  best of 3                                 */
 } fwi_batch_info;
 
 /* `autotune` flags of fwi_batch_plan_create. */

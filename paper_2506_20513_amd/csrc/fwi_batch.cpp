@@ -60,6 +60,8 @@ struct Step {
     OpKind kind;
     bool tail;
     int depth;                     // temporal depth of a stencil step
+    int lev;                       // forward steps: 0 no entry writes every level's
+                                   // Ez, 1 every entry does, 2 mixed
     int nm;
     unsigned nblocks;
     unsigned long long ctotal;     // copy steps: floats copied
@@ -299,6 +301,7 @@ void build_schedule(std::vector<Problem> &probs, char *ws, size_t area, Schedule
             s.kind = OP_CALL;
             s.tail = false;
             s.depth = 0;
+            s.lev = 0;
             s.nm = 0;
             s.nblocks = 0;
             s.ctotal = 0;
@@ -314,6 +317,7 @@ void build_schedule(std::vector<Problem> &probs, char *ws, size_t area, Schedule
             s.kind = OP_COPY;
             s.tail = false;
             s.depth = 0;
+            s.lev = 0;
             s.nm = 0;
             s.nblocks = 0;
             s.ctotal = 0;
@@ -341,6 +345,7 @@ void build_schedule(std::vector<Problem> &probs, char *ws, size_t area, Schedule
             s.kind = o.kind;
             s.tail = tail != 0;
             s.depth = depth;
+            s.lev = 0;
             s.nm = 0;
             s.nblocks = 0;
             s.ctotal = 0;
@@ -356,7 +361,13 @@ void build_schedule(std::vector<Problem> &probs, char *ws, size_t area, Schedule
                 const int Sq = q.kind == OP_FWD ? q.fa.S : q.aa.S;
                 s.nblocks += stream_blocks(Sq, tl);
                 S.boff.push_back(s.nblocks);
-                if (q.kind == OP_FWD) S.ftab.push_back(q.fa); else S.atab.push_back(q.aa);
+                if (q.kind == OP_FWD) {
+                    const int lq = q.fa.E_lev ? 1 : 0;
+                    s.lev = s.nm == 0 ? lq : (s.lev == lq ? lq : 2);
+                    S.ftab.push_back(q.fa);
+                } else {
+                    S.atab.push_back(q.aa);
+                }
                 ++s.nm;
             }
             if (s.nm == 0) {
@@ -379,7 +390,7 @@ hipError_t run_step(const Step &s, char *ws, hipStream_t st) {
     const unsigned *boff = reinterpret_cast<const unsigned *>(ws + s.boff_off);
     if (s.kind == OP_FWD)
         return launch_fwd_table(reinterpret_cast<const FwdStreamArgs *>(ws + s.tab_off), boff,
-                                s.nm, s.nblocks, s.depth, s.tail, st);
+                                s.nm, s.nblocks, s.depth, s.tail, s.lev, st);
     return launch_adj_table(reinterpret_cast<const AdjStreamArgs *>(ws + s.tab_off), boff,
                             s.nm, s.nblocks, s.depth, s.tail, st);
 }
@@ -543,13 +554,16 @@ extern "C" int fwi_batch_plan_create(int32_t n, const fwi_batch_problem *problem
         heights = {0};
     int depth = depths[0], rows = heights[0];
     if (depths.size() * heights.size() > 1) {
-        // time the first merged forward pass and the first merged adjoint
-        // pass of every candidate (best of 3 each); a gradient runs two
-        // forward passes (sweep and segment re-forward) and one adjoint pass
-        // per `depth` steps, so the cost per step is (2 fwd + adj) / depth.
-        // The adjoint pass runs on whatever state the workspace holds (all of
-        // it allocated); its time does not depend on the values, and every
-        // run of the plan clears that state first.
+        // time, for every candidate, the largest merged full-depth launch of
+        // each pass kind (best of 3 each): the forward sweep, the segment
+        // re-forward and the adjoint.  A gradient runs one of each per
+        // `depth` steps, so the cost per step is (sweep + re-forward +
+        // adjoint) / depth.  The largest launches are those where every
+        // problem takes part; the first adjoint launches hold only the
+        // longest problems.  The re-forward and adjoint passes run on
+        // whatever state the workspace holds (all of it allocated); their
+        // time does not depend on the values, and every run of the plan
+        // clears that state first.
         double best = 1e300;
         hipEvent_t e0, e1;
         if (hipEventCreate(&e0) != hipSuccess) return fail(FWI_EHIP);
@@ -585,17 +599,37 @@ extern "C" int fwi_batch_plan_create(int32_t n, const fwi_batch_problem *problem
                     if (run_step(S.steps[first], w, st) != hipSuccess) rc = FWI_EHIP;
                     ++first;
                 }
-                size_t fadj = first;
-                while (fadj < S.steps.size() && S.steps[fadj].kind != OP_ADJ) ++fadj;
-                if (rc != FWI_OK || first >= S.steps.size() || fadj >= S.steps.size()) {
+                // largest full-depth launch of a kind (forward: of a
+                // level-store choice), else the largest partial one
+                auto largest = [&](OpKind kind, int lev) {
+                    size_t best_k = S.steps.size();
+                    for (size_t k = first; k < S.steps.size(); ++k) {
+                        const Step &q = S.steps[k];
+                        if (q.kind != kind || (kind == OP_FWD && q.lev != lev)) continue;
+                        if (best_k == S.steps.size()) {
+                            best_k = k;
+                            continue;
+                        }
+                        const Step &b = S.steps[best_k];
+                        if ((b.tail && !q.tail) ||
+                            (b.tail == q.tail && q.nblocks > b.nblocks))
+                            best_k = k;
+                    }
+                    return best_k;
+                };
+                const size_t fsw = largest(OP_FWD, 0), fre = largest(OP_FWD, 1),
+                             fadj = largest(OP_ADJ, 0);
+                if (rc != FWI_OK || fsw >= S.steps.size() || fadj >= S.steps.size()) {
                     rc = rc == FWI_OK ? FWI_EHIP : rc;
                     break;
                 }
-                float tf = 0.f, ta = 0.f;
-                rc = time_step(S.steps[first], tf);
+                float tf = 0.f, tr = 0.f, ta = 0.f;
+                rc = time_step(S.steps[fsw], tf);
+                if (rc == FWI_OK && fre < S.steps.size()) rc = time_step(S.steps[fre], tr);
+                else tr = tf;
                 if (rc == FWI_OK) rc = time_step(S.steps[fadj], ta);
                 if (rc != FWI_OK) break;
-                const double cost = (2.0 * tf + ta) / dep;
+                const double cost = ((double)tf + tr + ta) / dep;
                 if (tuned < FWI_BATCH_MAX_TUNE) {
                     plan->info.tune_depth[tuned] = dep;
                     plan->info.tune_rows[tuned] = h;

@@ -451,7 +451,9 @@ __device__ __forceinline__ int table_entry(const unsigned *boff, int nm, unsigne
     return lo;
 }
 
-template <int K, bool TAIL>
+// LEV as in fwd_body: 0 or 1 when every problem of the launch makes the same
+// choice (fewer registers), 2 when they differ.
+template <int K, bool TAIL, int LEV>
 __global__ __launch_bounds__(64) void k_fwd_tab(const FwdStreamArgs *tab, const unsigned *boff,
                                                 int nm) {
     __shared__ float4 ring[K][64];
@@ -460,9 +462,9 @@ __global__ __launch_bounds__(64) void k_fwd_tab(const FwdStreamArgs *tab, const 
     const FwdStreamArgs a = load_const(tab, m);
     const WaveTile w = wave_tile<K>(a.tl, a.S, a.NX, a.npml, (int)(lb - ldc(boff, m)));
     if (w.edge)
-        fwd_body<K, true, TAIL, 2>(a, w, ring);
+        fwd_body<K, true, TAIL, LEV>(a, w, ring);
     else
-        fwd_body<K, false, TAIL, 2>(a, w, ring);
+        fwd_body<K, false, TAIL, LEV>(a, w, ring);
 }
 
 // ---------------------------------------------------------------------------
@@ -736,13 +738,26 @@ unsigned stream_blocks(int S, const Tiling &tl) {
     return (unsigned)S * tl.nstrip * tl.nband;
 }
 
+template <int K, int LEV>
+void launch_fwd_table_lev(const FwdStreamArgs *tab, const unsigned *boff, int nm,
+                          unsigned nblocks, bool tail, hipStream_t st) {
+    if (tail)
+        hipLaunchKernelGGL((k_fwd_tab<K, true, LEV>), dim3(nblocks), dim3(64), 0, st, tab, boff,
+                           nm);
+    else
+        hipLaunchKernelGGL((k_fwd_tab<K, false, LEV>), dim3(nblocks), dim3(64), 0, st, tab, boff,
+                           nm);
+}
+
 template <int K>
 hipError_t launch_fwd_table_depth(const FwdStreamArgs *tab, const unsigned *boff, int nm,
-                                  unsigned nblocks, bool tail, hipStream_t st) {
-    if (tail)
-        hipLaunchKernelGGL((k_fwd_tab<K, true>), dim3(nblocks), dim3(64), 0, st, tab, boff, nm);
+                                  unsigned nblocks, bool tail, int lev, hipStream_t st) {
+    if (lev == 0)
+        launch_fwd_table_lev<K, 0>(tab, boff, nm, nblocks, tail, st);
+    else if (lev == 1)
+        launch_fwd_table_lev<K, 1>(tab, boff, nm, nblocks, tail, st);
     else
-        hipLaunchKernelGGL((k_fwd_tab<K, false>), dim3(nblocks), dim3(64), 0, st, tab, boff, nm);
+        launch_fwd_table_lev<K, 2>(tab, boff, nm, nblocks, tail, st);
     return hipGetLastError();
 }
 
@@ -757,12 +772,13 @@ hipError_t launch_adj_table_depth(const AdjStreamArgs *tab, const unsigned *boff
 }
 
 hipError_t launch_fwd_table(const FwdStreamArgs *tab, const unsigned *boff, int nm,
-                            unsigned nblocks, int depth, bool tail, hipStream_t st) {
+                            unsigned nblocks, int depth, bool tail, int lev, hipStream_t st) {
+    if (lev < 0 || lev > 2) return hipErrorInvalidValue;
     if (nblocks == 0) return hipSuccess;
     if (depth == kDepthSmall)
-        return launch_fwd_table_depth<kDepthSmall>(tab, boff, nm, nblocks, tail, st);
+        return launch_fwd_table_depth<kDepthSmall>(tab, boff, nm, nblocks, tail, lev, st);
     if (depth == kDepthLarge)
-        return launch_fwd_table_depth<kDepthLarge>(tab, boff, nm, nblocks, tail, st);
+        return launch_fwd_table_depth<kDepthLarge>(tab, boff, nm, nblocks, tail, lev, st);
     return hipErrorInvalidValue;
 }
 
