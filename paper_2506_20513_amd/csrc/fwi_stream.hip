@@ -452,10 +452,15 @@ __device__ __forceinline__ int table_entry(const unsigned *boff, int nm, unsigne
 }
 
 // LEV as in fwd_body: 0 or 1 when every problem of the launch makes the same
-// choice (fewer registers), 2 when they differ.
+// choice (fewer registers), 2 when they differ.  Arguments read from the
+// table stay live in registers where kernel arguments would be reloaded, so
+// the depth-4 sweep would need 102 VGPRs (4 waves per SIMD); it is held to
+// 5 waves, which it reaches without spilling.
 template <int K, bool TAIL, int LEV>
-__global__ __launch_bounds__(64) void k_fwd_tab(const FwdStreamArgs *tab, const unsigned *boff,
-                                                int nm) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K == kDepthSmall && LEV == 0
+                                                                        ? 5
+                                                                        : 1))) void
+k_fwd_tab(const FwdStreamArgs *tab, const unsigned *boff, int nm) {
     __shared__ float4 ring[K][64];
     const unsigned lb = (unsigned)xcd_logical(blockIdx.x, gridDim.x);
     const int m = table_entry(boff, nm, lb);
