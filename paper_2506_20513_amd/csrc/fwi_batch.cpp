@@ -12,8 +12,8 @@
 // table), so small problems that could not fill the chip alone run side by
 // side.  The merged sequence is captured once in a HIP graph and replayed
 // by every run; the temporal depth of the passes and the row-band height of
-// the decomposition are chosen by timing candidates on the first merged
-// forward and adjoint passes.
+// the decomposition are chosen by timing candidates on the largest merged
+// sweep, re-forward and adjoint passes.
 #include "fwi_host.h"
 
 #include <algorithm>
