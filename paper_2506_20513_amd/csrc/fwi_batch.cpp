@@ -60,8 +60,8 @@ struct Step {
     OpKind kind;
     bool tail;
     int depth;                     // temporal depth of a stencil step
-    int lev;                       // forward steps: 0 no entry writes every level's
-                                   // Ez, 1 every entry does, 2 mixed
+    int lev;                       // forward steps: 1 if the entries write every
+                                   // level's Ez (segment re-forward), 0 if not
     int nm;
     unsigned nblocks;
     unsigned long long ctotal;     // copy steps: floats copied
@@ -338,14 +338,17 @@ void build_schedule(std::vector<Problem> &probs, char *ws, size_t area, Schedule
         }
         size_t j = i;
         while (j < ops.size() && ops[j].kind == o.kind && ops[j].key == o.key) ++j;
-        // full-depth and partial passes go to separate launches
+        // full-depth and partial passes go to separate launches, and so do
+        // forward passes that write every level's Ez and those that do not
         const int depth = o.kind == OP_FWD ? o.fa.tl.depth : o.aa.tl.depth;
-        for (int tail = 0; tail < 2; ++tail) {
+        for (int part = 0; part < 4; ++part) {
+            const int tail = part & 1, lev = part >> 1;
+            if (o.kind == OP_ADJ && lev) continue;
             Step s;
             s.kind = o.kind;
             s.tail = tail != 0;
             s.depth = depth;
-            s.lev = 0;
+            s.lev = lev;
             s.nm = 0;
             s.nblocks = 0;
             s.ctotal = 0;
@@ -357,17 +360,12 @@ void build_schedule(std::vector<Problem> &probs, char *ws, size_t area, Schedule
                 const Op &q = ops[k];
                 const int nlev = q.kind == OP_FWD ? q.fa.nlev : q.aa.nlev;
                 if ((nlev < depth) != (tail != 0)) continue;
+                if (q.kind == OP_FWD && (q.fa.E_lev != nullptr) != (lev != 0)) continue;
                 const Tiling &tl = q.kind == OP_FWD ? q.fa.tl : q.aa.tl;
                 const int Sq = q.kind == OP_FWD ? q.fa.S : q.aa.S;
                 s.nblocks += stream_blocks(Sq, tl);
                 S.boff.push_back(s.nblocks);
-                if (q.kind == OP_FWD) {
-                    const int lq = q.fa.E_lev ? 1 : 0;
-                    s.lev = s.nm == 0 ? lq : (s.lev == lq ? lq : 2);
-                    S.ftab.push_back(q.fa);
-                } else {
-                    S.atab.push_back(q.aa);
-                }
+                if (q.kind == OP_FWD) S.ftab.push_back(q.fa); else S.atab.push_back(q.aa);
                 ++s.nm;
             }
             if (s.nm == 0) {

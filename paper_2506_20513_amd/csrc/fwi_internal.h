@@ -204,8 +204,8 @@ unsigned stream_blocks(int S, const Tiling &tl);
 // arguments and boff[0..nm] (device) the prefix sums of their block counts,
 // nblocks = boff[nm].  depth: the passes' temporal depth (kDepthSmall or
 // kDepthLarge, the same for every problem of the launch); tail: the
-// problems advance fewer than depth levels.  lev (forward only): 0 if no
-// problem's entry has E_lev set, 1 if every one has, 2 if they differ.
+// problems advance fewer than depth levels.  lev (forward only): 1 if every
+// problem's entry has E_lev set (segment re-forward), 0 if none has.
 hipError_t launch_fwd_table(const FwdStreamArgs *tab, const unsigned *boff, int nm,
                             unsigned nblocks, int depth, bool tail, int lev, hipStream_t st);
 hipError_t launch_adj_table(const AdjStreamArgs *tab, const unsigned *boff, int nm,

@@ -222,9 +222,9 @@ __device__ __forceinline__ WaveTile wave_tile(const Tiling &tl, int S, int NX, i
 // H rows/columns that the E update never reads (Hx at j = NY-1, Hy at
 // i = NX-1) see a zero difference and stay zero, and ring Ez stays zero.
 // psi is a float4 (psi_hx, psi_hy, psi_ex, psi_ey).  LEV: 1 if the pass
-// writes every level's Ez (a.E_lev set), 0 if only the final state, 2 if
-// decided at run time; a fixed choice keeps the other stores' addresses out
-// of the scalar registers.
+// writes every level's Ez (a.E_lev set), 0 if only the final state; fixing
+// the choice at compile time keeps the other stores' addresses out of the
+// scalar registers.
 template <int K, bool EDGE, bool TAIL, int LEV>
 __device__ __forceinline__ void fwd_body(const FwdStreamArgs &a, const WaveTile &w,
                                          float4 (*ring)[64]) {
@@ -255,7 +255,8 @@ __device__ __forceinline__ void fwd_body(const FwdStreamArgs &a, const WaveTile 
     const float *Cap = a.Ca;
     const float *Csp = a.Cs;
     const int rlast = min(NY - 1, y1 + nlev - 1);
-    const bool lev = LEV == 2 ? a.E_lev != nullptr : LEV == 1;
+    static_assert(LEV == 0 || LEV == 1, "LEV is 0 or 1");
+    const bool lev = LEV == 1;
     float *const elev0 = lev ? a.E_lev + so : nullptr;   // level 0 slot of the shot
     const size_t lstr = a.lev_stride;
 
@@ -451,8 +452,8 @@ __device__ __forceinline__ int table_entry(const unsigned *boff, int nm, unsigne
     return lo;
 }
 
-// LEV as in fwd_body: 0 or 1 when every problem of the launch makes the same
-// choice (fewer registers), 2 when they differ.  Arguments read from the
+// LEV as in fwd_body, 0 or 1: the problems of one launch all write every
+// level's Ez (segment re-forward) or none does (sweep).  Arguments read from the
 // table stay live in registers where kernel arguments would be reloaded, so
 // the depth-4 sweep would need 102 VGPRs (4 waves per SIMD); it is held to
 // 5 waves, which it reaches without spilling.
@@ -759,10 +760,8 @@ hipError_t launch_fwd_table_depth(const FwdStreamArgs *tab, const unsigned *boff
                                   unsigned nblocks, bool tail, int lev, hipStream_t st) {
     if (lev == 0)
         launch_fwd_table_lev<K, 0>(tab, boff, nm, nblocks, tail, st);
-    else if (lev == 1)
-        launch_fwd_table_lev<K, 1>(tab, boff, nm, nblocks, tail, st);
     else
-        launch_fwd_table_lev<K, 2>(tab, boff, nm, nblocks, tail, st);
+        launch_fwd_table_lev<K, 1>(tab, boff, nm, nblocks, tail, st);
     return hipGetLastError();
 }
 
@@ -778,7 +777,7 @@ hipError_t launch_adj_table_depth(const AdjStreamArgs *tab, const unsigned *boff
 
 hipError_t launch_fwd_table(const FwdStreamArgs *tab, const unsigned *boff, int nm,
                             unsigned nblocks, int depth, bool tail, int lev, hipStream_t st) {
-    if (lev < 0 || lev > 2) return hipErrorInvalidValue;
+    if (lev != 0 && lev != 1) return hipErrorInvalidValue;
     if (nblocks == 0) return hipSuccess;
     if (depth == kDepthSmall)
         return launch_fwd_table_depth<kDepthSmall>(tab, boff, nm, nblocks, tail, lev, st);

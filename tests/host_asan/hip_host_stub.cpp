@@ -116,14 +116,14 @@ hipError_t launch_adj_stream(const AdjStreamArgs &a, hipStream_t) {
 }
 unsigned stream_blocks(int S, const Tiling &tl) { return (unsigned)S * tl.nstrip * tl.nband; }
 // The forward table is read, so the sanitizer checks it and its block
-// offsets, and the launch's level-store choice is checked against its entries.
+// offsets, and every entry must make the launch's level-store choice.
 hipError_t launch_fwd_table(const FwdStreamArgs *tab, const unsigned *boff, int nm,
                             unsigned nblocks, int, bool, int lev, hipStream_t) {
     if (nm < 1 || boff[0] != 0 || boff[nm] != nblocks) return hipErrorInvalidValue;
-    int n_lev = 0;
-    for (int m = 0; m < nm; ++m) n_lev += tab[m].E_lev != nullptr;
-    const int want = n_lev == 0 ? 0 : n_lev == nm ? 1 : 2;
-    return lev == want ? hipSuccess : hipErrorInvalidValue;
+    if (lev != 0 && lev != 1) return hipErrorInvalidValue;
+    for (int m = 0; m < nm; ++m)
+        if ((tab[m].E_lev != nullptr) != (lev == 1)) return hipErrorInvalidValue;
+    return hipSuccess;
 }
 hipError_t launch_adj_table(const AdjStreamArgs *, const unsigned *, int, unsigned, int, bool,
                             hipStream_t) {
