@@ -280,7 +280,8 @@ void build_schedule(std::vector<Problem> &probs, char *ws, size_t area, Schedule
             ncc += o.cp.size() + 1;   // upper bound: one extra sum per step
         }
     }
-    nb = nf + na + 2 * ops.size();    // upper bound: one extra offset per group
+    nb = nf + na + 2 * ops.size();    // upper bound: one offset per entry plus one per
+                                      // launch, and every launch holds an entry
     S.f_off = area;
     S.a_off = S.f_off + align_up(nf * sizeof(FwdStreamArgs));
     S.b_off = S.a_off + align_up(na * sizeof(AdjStreamArgs));
